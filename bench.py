@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Throughput of the dimension-lifted FFT on one MI355X.
+
+Workload: complex64 1-D transforms of n = 2^24 lifted to 4096 x 4096, inputs
+iid standard normal (seeded), forward (sign -1) and inverse (sign +1).
+One step = one forward transform of one buffer set plus one inverse transform
+of the next buffer set, so every stage of the path (both passes, the
+inter-pass weights, the redistribution and the natural-order store) runs in
+both directions.  Buffer sets are rotated so that no transform reads an input
+that is still resident in the 256 MB last-level cache from an earlier step.
+
+Prints one JSON line (rank 0).  GFLOP/s uses the conventional 5 n log2 n flops
+per transform; HBM GB/s uses the method's algorithmic traffic (each pass
+reads and writes n elements: 32 n bytes per complex64 transform).
+
+    python bench.py [--steps K] [--warmup W] [--log2n 24] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("GFLOP/s (5n·log2n) + HBM GB/s % peak, c64 n=2^24; fwd+bwd and batched "
+          "vs plain")
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c64_n2p24.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("liftfft.hip", "fft_engine.hpp"):
+        with open(os.path.join(ROOT, "paper_0811_2535_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, launches_bytes: float):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None if absent or taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(x0, x1, y0_gpu, y1_gpu):
+    """The FP64 oracle (untuned, one thread) on one forward and one inverse
+    transform of the benchmark's own inputs; also returns the parity of the
+    GPU outputs of those two transforms."""
+    import numpy as np
+
+    import oracle
+    n = x0.size
+    t0 = time.perf_counter()
+    r0 = oracle.fft(x0.astype(np.complex128), -1)
+    r1 = oracle.fft(x1.astype(np.complex128), 1)
+    dt = time.perf_counter() - t0
+    flops = 2 * 5.0 * n * math.log2(n)
+    base = {"value": round(flops / dt / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": "one forward + one inverse c64 n=2^%d transform (FP64 recursive radix-2, "
+                      "1 thread), %.2f s" % (int(math.log2(n)), dt),
+            "seconds": round(dt, 3)}
+    parity = {"rel_l2_forward": oracle.rel_l2(y0_gpu, r0), "rel_l2_inverse": oracle.rel_l2(y1_gpu, r1),
+              "tolerance": 1e-6}
+    return base, parity
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--log2n", type=int, default=24)
+    ap.add_argument("--sets", type=int, default=4, help="buffer sets rotated between transforms")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; --gpus %d is not supported "
+              "(transforms shard across GPUs without exchange for batches, and with one "
+              "all-to-all for a single large transform; neither is built here)" % args.gpus,
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_0811_2535_amd as lf
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    lf.lib()  # fail loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = 1 << args.log2n
+    S = max(2, args.sets)
+
+    print("[bench] generating %d input sets of n=2^%d c64" % (S, args.log2n), file=sys.stderr,
+          flush=True)
+    host_inputs = [datagen.signals(n, 1, np.complex64, "normal", 2 + 1000 * s)[0]
+                   for s in range(S)]
+    xs = [torch.from_numpy(h).to(dev) for h in host_inputs]
+    ys = [torch.empty_like(x) for x in xs]
+    plan = lf.Plan(n, 1, torch.complex64)
+    info = plan.info()
+    stream = torch.cuda.current_stream(dev)
+
+    def step(i):
+        a, b = (2 * i) % S, (2 * i + 1) % S
+        plan.execute(xs[a], ys[a], -1, stream)
+        plan.execute(xs[b], ys[b], 1, stream)
+
+    print("[bench] warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+
+    print("[bench] timing %d steps" % args.steps, file=sys.stderr, flush=True)
+    plan.set_timing(True)
+    plan.read_timing(reset=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        step(args.warmup + i)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = ev0.elapsed_time(ev1)
+    kms, kcnt = plan.read_timing(reset=True)
+    plan.set_timing(False)
+
+    ms_step = ms_total / args.steps
+    flops_step = 2 * 5.0 * n * math.log2(n)
+    esize = 8
+    alg_bytes_step = 2 * (32 if info["passes"] == 2 else 16) * n * esize // 8
+    gflops = flops_step / (ms_step * 1e-3) / 1e9
+    gbs = alg_bytes_step / (ms_step * 1e-3) / 1e9
+
+    # Dominant kernel: the pass with the larger average launch duration.
+    names = ["pass1", "pass2"] if info["passes"] == 2 else ["single"]
+    avg = [kms[k] / kcnt[k] if kcnt[k] else 0.0 for k in range(len(names))]
+    kd = max(range(len(names)), key=lambda k: avg[k])
+    bytes_per_launch = 2 * n * esize  # one read + one write of n elements
+    achieved = bytes_per_launch / (avg[kd] * 1e-3) / 1e9
+    traffic = load_traffic(names[kd], bytes_per_launch)
+
+    # Output parity of the transforms timed (step 0 sets: forward of set 0,
+    # inverse of set 1), from the same buffers.
+    y0 = ys[0].cpu().numpy()
+    y1 = ys[1].cpu().numpy()
+    result = {
+        "metric": METRIC,
+        "value": round(gflops, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "c64 1-D FFT n=2^%d lifted %dx%d, one forward + one inverse per step, "
+                        "N(0,1) inputs seeds 2+1000s, %d rotating buffer sets"
+                        % (args.log2n, 1 << info["log2_p"], 1 << info["log2_q"], S),
+            "n": n, "batch": 1, "passes": info["passes"], "log2_p": info["log2_p"],
+            "log2_q": info["log2_q"], "radix": info["radix"],
+            "lines_per_block": [info["lines_per_block_pass1"], info["lines_per_block_pass2"]],
+        },
+        "hbm": {
+            "alg_bytes_per_step": alg_bytes_step,
+            "gbps": round(gbs, 1),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "effective_gbps_16n": round(gbs / 2, 1),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": names[kd],
+            "kernel_avg_us": round(avg[kd] * 1e3, 2),
+            "kernels_avg_us": {names[k]: round(avg[k] * 1e3, 2) for k in range(len(names))},
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "alg_bytes_per_launch": bytes_per_launch,
+        },
+        "wall_s": round(wall, 4),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (FP64 oracle, 1 thread)", file=sys.stderr, flush=True)
+        base, parity = cpu_baseline(host_inputs[0], host_inputs[1], y0, y1)
+        result["cpu_baseline"] = base
+        result["parity"] = parity
+    plan.destroy()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,159 @@
+/*
+ * liftfft -- dimension-lifted 1-D complex FFT for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libliftfft.so.  No C++ or framework types cross this boundary:
+ * sizes are int64_t, buffers are plain device pointers, the stream is an
+ * opaque hipStream_t passed as void*.
+ *
+ * The transform (Hunt, Mullin, Rosenkrantz, Raynolds, "A Transformation-Based
+ * Approach for the Design of Parallel/Distributed Scientific Software: the
+ * FFT", Section 2.1, Fig. 2.1: input x in C^n, n = 2^t, t >= 1; output the FFT
+ * of x) is, for every transform b < batch,
+ *
+ *     out[b*n + k] = sum_{j<n} in[b*n + j] * exp(sign * 2*pi*i * j*k / n),
+ *
+ * unnormalized in both directions, natural order in and out.  sign = -1 is
+ * the usual forward transform; sign = +1 is the exponent the paper's own loops
+ * use (Section 3, weights EXP(2*pi*i*row/L)) and is the adjoint of sign = -1.
+ *
+ * Method (Sections 4.2-4.8: the stage loop split at a breakpoint into a block
+ * phase and a cyclic phase joined by a block-to-cyclic redistribution,
+ * Fig. 4.9, Fig. 5.3): n is lifted to a p x q array with n = p*q,
+ * j = j1 + p*j2, k = k2 + q*k1.  Pass 1 runs the q-point transforms over j2
+ * for each j1 (the block phase), multiplies by w_n^(sign*j1*k2) and writes a
+ * tiled scratch array (the redistribution); pass 2 runs the p-point
+ * transforms over j1 for each k2 (the cyclic phase) and stores X[k2 + q*k1]
+ * in natural order.  Lengths that fit one workgroup run in a single pass.
+ *
+ * Data layout: interleaved complex; FFT_C64 = float2 {re, im} (8 bytes),
+ * FFT_C128 = double2 {re, im} (16 bytes).  Transform b occupies elements
+ * [b*n, (b+1)*n).
+ *
+ * Threading: a plan may be used from one host thread at a time; executes on
+ * one plan must be ordered on one stream (they share the plan's scratch).
+ * Different plans are independent.
+ */
+#ifndef LIFTFFT_H
+#define LIFTFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fft_plan fft_plan; /* opaque; owns scratch and twiddle tables */
+
+/* Element types. */
+enum { FFT_C64 = 0, FFT_C128 = 1 };
+
+/* Status codes.  Every argument and capacity check runs on the host before
+ * any device work, so an error return means nothing was launched. */
+enum {
+    FFT_OK = 0,
+    FFT_E_SIZE = -1,        /* n not a power of two, n < 2, batch < 1, size overflow */
+    FFT_E_DTYPE = -2,       /* unknown element type */
+    FFT_E_SIGN = -3,        /* sign not -1 or +1 */
+    FFT_E_NULL = -4,        /* required pointer is NULL */
+    FFT_E_ALIGN = -5,       /* buffer not aligned to its element size */
+    FFT_E_OOM = -6,         /* device allocation failed (nothing leaked) */
+    FFT_E_HIP = -7,         /* a HIP runtime call or kernel launch failed */
+    FFT_E_UNSUPPORTED = -8, /* valid request outside what this build supports */
+    FFT_E_ARG = -9          /* other invalid argument (options, precision mode) */
+};
+
+/* Largest supported log2(n) per element type (two-level lift). */
+#define FFT_MAX_LOG2N_C64 24
+#define FFT_MAX_LOG2N_C128 24
+
+/*
+ * Create a plan for `batch` transforms of length `n` of element type `dtype`.
+ * Validates the arguments, chooses the lift (single pass when n fits one
+ * workgroup, else p x q with q >= p), allocates the scratch array (n*batch
+ * elements, two-pass plans only) and the twiddle tables, and fills the tables
+ * on the current device with an FP64 kernel (each entry computed directly
+ * from its integer exponent, rounded once to the element type).  Synchronous.
+ * On success *plan_out owns the plan (release with fft_plan_destroy); on
+ * failure *plan_out is set to NULL and nothing is leaked.
+ * The plan is bound to the device current at creation.
+ */
+int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out);
+
+/*
+ * Plan options for fft_plan_create_ex (zero-initialise, then set fields;
+ * a zero field means "library default").
+ *   log2_p        force the lift n = p*q with p = 2^log2_p (1 <= log2_p < t);
+ *                 forces the two-pass path even when n fits one workgroup.
+ *   radix         largest butterfly radix used inside each pass: 2, 4, 8
+ *                 or 16 (default 16).  radix = 2 gives the paper's plain
+ *                 radix-2 stage loop within each pass.
+ *   lines_per_block  transforms per workgroup in pass 1 (0 = default).
+ */
+typedef struct fft_plan_opts {
+    int32_t log2_p;
+    int32_t radix;
+    int32_t lines_per_block;
+    int32_t reserved[5];
+} fft_plan_opts;
+
+/* As fft_plan_create with explicit options (opts may be NULL). */
+int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts *opts,
+                       fft_plan **plan_out);
+
+/*
+ * Execute the planned transforms: out = F_sign(in), as defined above.
+ *   in, out   device pointers to n*batch elements, aligned to the element
+ *             size; in == out is allowed (pass 1 writes the plan's scratch).
+ *             Partial overlap of in and out is not allowed.
+ *   sign      -1 or +1.
+ *   stream    hipStream_t to launch on (NULL = the null stream).
+ * Asynchronous: returns after enqueueing the kernels; no host synchronisation
+ * and no allocation.  Returns FFT_E_HIP if a launch fails.
+ */
+int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void *stream);
+
+/* Release a plan.  NULL-safe.  The caller must have synchronised every stream
+ * that used the plan. */
+int fft_plan_destroy(fft_plan *plan);
+
+/* Static description of a status code (never NULL). */
+const char *fft_strerror(int code);
+
+/*
+ * Plan description, for tests and benchmarks.
+ *   passes      1 or 2
+ *   log2_p      lift: p = 2^log2_p (0 for single-pass plans)
+ *   log2_q      lift: q = 2^log2_q (single pass: log2 n)
+ *   radix       largest butterfly radix used
+ *   lines_per_block_pass1, lines_per_block_pass2
+ *   scratch_bytes, table_bytes   device memory the plan owns
+ */
+typedef struct fft_plan_info {
+    int64_t n, batch;
+    int32_t dtype, passes, log2_p, log2_q, radix;
+    int32_t lines_per_block_pass1, lines_per_block_pass2;
+    int64_t scratch_bytes, table_bytes;
+} fft_plan_info;
+
+int fft_plan_get_info(const fft_plan *plan, fft_plan_info *info);
+
+/*
+ * Per-kernel timing, for benchmarks.  While enabled, fft_execute records a
+ * HIP event before and after each kernel it launches, on the execute stream;
+ * fft_plan_read_timing synchronises on the last recorded event and returns,
+ * for pass k (k = 0, 1), the summed duration in milliseconds and the launch
+ * count since the last reset.  Disabled by default (no events recorded).
+ */
+int fft_plan_set_timing(fft_plan *plan, int enable);
+int fft_plan_read_timing(fft_plan *plan, double ms_out[2], int64_t launches_out[2],
+                         int reset);
+
+/* ABI version of this header (major*100 + minor). */
+#define LIFTFFT_ABI_VERSION 100
+int fft_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIFTFFT_H */

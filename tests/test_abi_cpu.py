@@ -1,0 +1,88 @@
+"""Host-side checks of the C-ABI library that need no GPU: every symbol the
+header declares is exported, and argument validation that runs before any
+device call returns the documented status codes."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "liftfft.h")
+
+
+def _lib():
+    from paper_0811_2535_amd import binding
+    try:
+        return binding.lib()
+    except binding.LibraryNotBuilt:
+        pytest.skip("libliftfft.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fft_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("fft_plan_create", "fft_execute", "fft_plan_destroy", "fft_strerror"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported():
+    L = _lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_binding_lists_match_header():
+    from paper_0811_2535_amd import binding
+    assert sorted(binding.EXPORTED) == declared_functions()
+
+
+def test_abi_version():
+    assert _lib().fft_abi_version() == 100
+
+
+def test_strerror_covers_codes():
+    L = _lib()
+    for code in range(-9, 1):
+        s = L.fft_strerror(code)
+        assert s and s != b"unknown status code", code
+    assert L.fft_strerror(-1234) == b"unknown status code"
+
+
+@pytest.mark.parametrize("n,batch,dtype,want", [
+    (0, 1, 0, -1), (1, 1, 0, -1), (3, 1, 0, -1), (1000, 1, 0, -1), (-8, 1, 0, -1),
+    (1024, 0, 0, -1), (1024, -5, 1, -1), (1024, 1, 2, -2), (1024, 1, -1, -2),
+    (1 << 25, 1, 0, -8), (1 << 30, 1, 1, -8), (1 << 20, 1 << 60, 0, -1),
+])
+def test_create_validation(n, batch, dtype, want):
+    L = _lib()
+    h = ctypes.c_void_p(123)
+    assert L.fft_plan_create(n, batch, dtype, ctypes.byref(h)) == want
+    assert h.value is None  # *plan_out cleared on failure
+
+
+def test_create_rejects_bad_options():
+    from paper_0811_2535_amd.binding import PlanOpts
+    L = _lib()
+    h = ctypes.c_void_p()
+    cases = [(PlanOpts(0, 3, 0), -9), (PlanOpts(0, 4, 0), -8), (PlanOpts(10, 0, 0), -9),
+             (PlanOpts(-1, 0, 0), -9), (PlanOpts(0, 0, 3), -9), (PlanOpts(0, 32, 0), -9)]
+    for opts, want in cases:
+        assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(opts), ctypes.byref(h)) == want
+    bad = PlanOpts(0, 0, 0)
+    bad.reserved[2] = 1
+    assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(bad), ctypes.byref(h)) == -9
+    assert L.fft_plan_create(1024, 1, 0, None) == -4
+
+
+def test_null_plan_paths():
+    L = _lib()
+    assert L.fft_execute(None, None, None, -1, None) == -4
+    assert L.fft_plan_destroy(None) == 0
+    assert L.fft_plan_get_info(None, None) == -4
+    assert L.fft_plan_set_timing(None, 1) == -4
