@@ -89,6 +89,9 @@ def main() -> int:
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--sets", type=int, default=4, help="buffer sets rotated between transforms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-reps", type=int, default=10,
+                    help="device-to-device copies of one pass's bytes, timed for context and "
+                         "used as the known-size reference kernel for HBM counters")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -164,6 +167,25 @@ def main() -> int:
     achieved = bytes_per_launch / (avg[kd] * 1e-3) / 1e9
     traffic = load_traffic(names[kd], bytes_per_launch)
 
+    # Reference: a plain streaming kernel over n complex64 elements (reads 8n,
+    # writes 8n bytes, the same algorithmic traffic as one pass), rotated over
+    # the sets.  torch.neg is used rather than copy_ so the reference is an
+    # ordinary elementwise kernel with a name of its own in profiles.
+    copy_gbs = None
+    if args.copy_reps > 0:
+        dst = [torch.empty_like(x) for x in xs]
+        for i in range(2):
+            torch.neg(xs[(i + 1) % S], out=dst[i % S])
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        c0.record(stream)
+        for i in range(args.copy_reps):
+            torch.neg(xs[(i + 1) % S], out=dst[i % S])
+        c1.record(stream)
+        torch.cuda.synchronize()
+        copy_gbs = 2 * n * esize * args.copy_reps / (c0.elapsed_time(c1) * 1e-3) / 1e9
+        del dst
+
     # Output parity of the transforms timed (step 0 sets: forward of set 0,
     # inverse of set 1), from the same buffers.
     y0 = ys[0].cpu().numpy()
@@ -194,6 +216,7 @@ def main() -> int:
             "gbps": round(gbs, 1),
             "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
             "effective_gbps_16n": round(gbs / 2, 1),
+            "copy_gbps_same_gpu": round(copy_gbs, 1) if copy_gbs else None,
         },
         "roofline": {
             "bound": "hbm",

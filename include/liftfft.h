@@ -87,13 +87,20 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out);
  *   radix         largest butterfly radix used inside each pass: 2, 4, 8
  *                 or 16 (default 16).  radix = 2 gives the paper's plain
  *                 radix-2 stage loop within each pass.
- *   lines_per_block  transforms per workgroup in pass 1 (0 = default).
+ *   lines_per_block   lines (independent short transforms) per workgroup in
+ *                     pass 1, or in the single pass (0 = default; power of two).
+ *   lines_per_block2  lines per workgroup in pass 2 (0 = default; power of two).
+ *   flags             FFT_OPT_NO_XCD_REMAP: keep the hardware workgroup order
+ *                     instead of giving each XCD a contiguous range of tiles.
  */
+enum { FFT_OPT_NO_XCD_REMAP = 1 };
 typedef struct fft_plan_opts {
     int32_t log2_p;
     int32_t radix;
     int32_t lines_per_block;
-    int32_t reserved[5];
+    int32_t lines_per_block2;
+    int32_t flags;
+    int32_t reserved[3];
 } fft_plan_opts;
 
 /* As fft_plan_create with explicit options (opts may be NULL). */
@@ -125,13 +132,20 @@ const char *fft_strerror(int code);
  *   log2_p      lift: p = 2^log2_p (0 for single-pass plans)
  *   log2_q      lift: q = 2^log2_q (single pass: log2 n)
  *   radix       largest butterfly radix used
- *   lines_per_block_pass1, lines_per_block_pass2
- *   scratch_bytes, table_bytes   device memory the plan owns
+ *   lines_per_block_pass1/2    lines (short transforms) per tile
+ *   grid_pass1/2               persistent workgroups launched
+ *   threads_pass1/2            workgroup size
+ *   lds_bytes_pass1/2          dynamic LDS per workgroup
+ *   scratch_bytes, table_bytes device memory the plan owns
+ * Pass-2 fields are 0 for single-pass plans.
  */
 typedef struct fft_plan_info {
     int64_t n, batch;
     int32_t dtype, passes, log2_p, log2_q, radix;
     int32_t lines_per_block_pass1, lines_per_block_pass2;
+    int32_t grid_pass1, grid_pass2;
+    int32_t threads_pass1, threads_pass2;
+    int64_t lds_bytes_pass1, lds_bytes_pass2;
     int64_t scratch_bytes, table_bytes;
 } fft_plan_info;
 

@@ -45,7 +45,8 @@ class FFTError(RuntimeError):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("log2_p", ctypes.c_int32), ("radix", ctypes.c_int32),
-                ("lines_per_block", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("lines_per_block", ctypes.c_int32), ("lines_per_block2", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -54,6 +55,9 @@ class PlanInfo(ctypes.Structure):
                 ("log2_p", ctypes.c_int32), ("log2_q", ctypes.c_int32),
                 ("radix", ctypes.c_int32), ("lines_per_block_pass1", ctypes.c_int32),
                 ("lines_per_block_pass2", ctypes.c_int32),
+                ("grid_pass1", ctypes.c_int32), ("grid_pass2", ctypes.c_int32),
+                ("threads_pass1", ctypes.c_int32), ("threads_pass2", ctypes.c_int32),
+                ("lds_bytes_pass1", ctypes.c_int64), ("lds_bytes_pass2", ctypes.c_int64),
                 ("scratch_bytes", ctypes.c_int64), ("table_bytes", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
@@ -122,12 +126,14 @@ class Plan:
     Thin wrapper over fft_plan_create_ex / fft_execute / fft_plan_destroy."""
 
     def __init__(self, n: int, batch: int = 1, dtype=torch.complex64, log2_p: int = 0,
-                 radix: int = 0, lines_per_block: int = 0):
+                 radix: int = 0, lines_per_block: int = 0, lines_per_block2: int = 0,
+                 flags: int = 0):
         self._h = ctypes.c_void_p()
         self.n, self.batch = int(n), int(batch)
         self.dtype_code = dtype_code(dtype)
         self.torch_dtype = torch.complex64 if self.dtype_code == FFT_C64 else torch.complex128
-        opts = PlanOpts(int(log2_p), int(radix), int(lines_per_block))
+        opts = PlanOpts(int(log2_p), int(radix), int(lines_per_block), int(lines_per_block2),
+                        int(flags))
         rc = lib().fft_plan_create_ex(self.n, self.batch, self.dtype_code, ctypes.byref(opts),
                                       ctypes.byref(self._h))
         _check(rc, "fft_plan_create_ex(n=%d, batch=%d)" % (self.n, self.batch))

@@ -1,22 +1,22 @@
-// Device-side FFT engine for gfx950: complex helpers, DFT codelets and the
-// workgroup-tile transform used by every pass kernel.
+// Device-side FFT engine for gfx950: complex helpers, DFT codelets, the radix
+// schedule, the LDS layout and the workgroup-tile transform used by every
+// pass kernel.
 //
-// A workgroup owns T "lines" (independent N-point transforms) at once.  Each
-// line is processed by TPL = N/E threads holding E = min(16, N) complex values
-// in registers.  The stage loop is the paper's stage loop (Section 2.1,
-// Fig. 2.1: one butterfly stage per doubling of the column length) regrouped
-// into radix-R stages, R <= 16: each radix-R stage is R-1 radix-2 stages done
-// at once in registers, i.e. the same dimension lifting the paper applies
-// between processors (Section 4.2), applied here between the register file
-// and LDS.  Stages are self-sorting (Stockham form), so no bit-reversal pass
-// is needed: for stage s with radix R and Ns = product of the earlier radices,
-// butterfly b < N/R reads elements b + r*(N/R), multiplies element r by
-// w_{Ns*R}^(r*(b mod Ns)), does an R-point DFT and writes element r to
+// A workgroup owns T "lines" (independent N-point transforms).  Each line is
+// processed by TPL = N/E threads holding E = min(16, N) complex values in
+// registers.  The stage loop is the paper's stage loop (Section 2.1, Fig. 2.1:
+// one butterfly stage per doubling of the column length) regrouped into
+// radix-R stages, R <= 16: a radix-R stage is log2(R) radix-2 stages done at
+// once in registers -- the same dimension lifting the paper applies between
+// processors (Section 4.2), applied here between the register file and LDS.
+// Stages are self-sorting (Stockham form), so no bit-reversal pass is needed:
+// for stage s with radix R and Ns = product of the earlier radices, butterfly
+// b < N/R reads elements b + r*(N/R), multiplies element r by
+// w_{Ns*R}^(-r*(b mod Ns)), does an R-point DFT and writes element r to
 // (b div Ns)*Ns*R + (b mod Ns) + r*Ns.  Data moves between stages through LDS.
 //
 // All transforms here use the exponent sign -1; sign +1 is obtained by
-// conjugating on load and on store (F_+(x) = conj(F_-(conj x))), which the
-// pass kernels do with a runtime flag.
+// conjugating on load and on store (F_+(x) = conj(F_-(conj x))).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -40,18 +40,18 @@ template <typename C> __device__ __forceinline__ C csub(C a, C b) { return mk<C>
 template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
     return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-// a * conj(w): multiply by the sign -1 twiddle when w holds the +1 root.
+// a * conj(w): multiply by the sign -1 root when w holds the +1 root.
 template <typename C> __device__ __forceinline__ C cmulc(C a, C w) {
     return mk<C>(a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y);
 }
 // a * (-i)
 template <typename C> __device__ __forceinline__ C mul_mi(C a) { return mk<C>(a.y, -a.x); }
-template <typename C> __device__ __forceinline__ C conj_if(C a, bool c) {
-    return c ? mk<C>(a.x, -a.y) : a;
+// Imaginary part times a uniform +1 or -1 (exact): conjugation on demand.
+template <typename C> __device__ __forceinline__ C scale_im(C a, decltype(C::x) s) {
+    return mk<C>(a.x, a.y * s);
 }
 
-// Multiply by w_16^(-e) (sign -1 root), e in 0..15, with the trivial cases
-// folded at compile time.
+// Multiply by w_16^(-e) (sign -1 root), e in 0..15, trivial cases folded.
 template <int e, typename C> __device__ __forceinline__ C rot16(C a) {
     using R = decltype(C::x);
     constexpr R c1 = R(0.92387953251128675613); // cos(pi/8)
@@ -123,7 +123,6 @@ template <typename C> __device__ __forceinline__ void dft16(C *v) {
         a[4 * r2 + 2] = x2;
         a[4 * r2 + 3] = x3;
     }
-    // a[4*r2 + k1] *= w_16^(-r2*k1)
     a[5] = rot16<1>(a[5]);
     a[6] = rot16<2>(a[6]);
     a[7] = rot16<3>(a[7]);
@@ -152,97 +151,177 @@ template <int R, typename C> __device__ __forceinline__ void dft(C *v) {
     else dft16(v);
 }
 
-// Radix schedule for an N-point line with largest radix RMAX: as many RMAX
-// stages as fit, plus one smaller stage for the remainder, placed second so
-// that the first and last stages (the ones touching global memory) use RMAX.
-template <int N, int RMAX> struct Sched {
-    static constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
-    static constexpr int LOGN = ilog2(N);
-    static constexpr int LOGR = ilog2(RMAX < N ? RMAX : N);
-    static constexpr int FULL = LOGN / LOGR;
-    static constexpr int REM = LOGN % LOGR;
-    static constexpr int NSTAGES = FULL + (REM ? 1 : 0);
-    static constexpr int radix(int s) {
-        return (REM && s == 1) ? (1 << REM) : (1 << LOGR);
-    }
-    static constexpr int ns(int s) { // product of the radices before stage s
-        int p = 1;
-        for (int i = 0; i < s; ++i) p *= radix(i);
-        return p;
-    }
-    static constexpr int E = N < 16 ? N : 16;   // values per thread
-    static constexpr int TPL = N / E;           // threads per line
-    static_assert(N >= 2 && (N & (N - 1)) == 0, "N must be a power of two >= 2");
-    static_assert(E % (1 << LOGR) == 0, "radix must divide the values per thread");
-};
+// ---------------------------------------------------------------------------
+// Radix schedule and LDS layout.  Plain constexpr functions of (N, RMAX, ...)
+// so the host computes the same sizes the kernels use.
+//
+// Schedule: as many RMAX stages as fit plus one smaller stage for the
+// remainder, placed second so that the first and last stages (the ones that
+// touch global memory) use the full radix.
+__host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+__host__ __device__ constexpr int vals_per_thread(int N) { return N < 16 ? N : 16; }
+__host__ __device__ constexpr int sched_logr(int N, int RMAX) { return ilog2c(RMAX < N ? RMAX : N); }
+__host__ __device__ constexpr int sched_nstages(int N, int RMAX) {
+    return ilog2c(N) / sched_logr(N, RMAX) + (ilog2c(N) % sched_logr(N, RMAX) ? 1 : 0);
+}
+__host__ __device__ constexpr int sched_radix(int N, int RMAX, int s) {
+    return (ilog2c(N) % sched_logr(N, RMAX) && s == 1) ? (1 << (ilog2c(N) % sched_logr(N, RMAX)))
+                                                        : (1 << sched_logr(N, RMAX));
+}
+__host__ __device__ constexpr int sched_ns(int N, int RMAX, int s) {
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= sched_radix(N, RMAX, i);
+    return p;
+}
 
-// LDS addressing.  LINE_MINOR (pass kernels, lanes sweep the T lines first):
-// element e of line c lives at pad(e)*T + c.  Otherwise (single-pass
-// kernel, lanes sweep one line first): c*PITCH + pad(e).  pad() inserts one
-// slot every 16 elements to spread the strided Stockham writes over banks.
-__device__ __forceinline__ int pad16(int e) { return e + (e >> 4); }
+// Tile: line c occupies [c*PITCH, c*PITCH + N + N/16); element e sits at
+// e + e/16 within its line (one spare slot per 16 elements spreads the
+// strided Stockham writes over the banks), and the pitch is 8 (mod 32)
+// elements so that the lines of one wavefront start in different banks.
+__host__ __device__ constexpr int line_pitch(int N) {
+    return (N + N / 16) + ((8 - (N + N / 16) % 32) + 32) % 32;
+}
+// Stage twiddles w_M^(r*k), M = Ns*R, k < Ns, r < R: with k = klo + 16*khi,
+// w_M^(r*k) = LO[klo][r] * HI[khi][r], LO[klo][r] = w_M^(r*klo) (klo < 16),
+// HI[khi][r] = w_{M/16}^(r*khi) (khi < Ns/16).  Rows padded to R+1 entries.
+__host__ __device__ constexpr int tw_lo_rows(int N, int RMAX, int s) {
+    return sched_ns(N, RMAX, s) < 16 ? sched_ns(N, RMAX, s) : 16;
+}
+__host__ __device__ constexpr int tw_hi_rows(int N, int RMAX, int s) {
+    return sched_ns(N, RMAX, s) > 16 ? sched_ns(N, RMAX, s) / 16 : 0;
+}
+__host__ __device__ constexpr int tw_stage_size(int N, int RMAX, int s) {
+    return (tw_lo_rows(N, RMAX, s) + tw_hi_rows(N, RMAX, s)) * (sched_radix(N, RMAX, s) + 1);
+}
+__host__ __device__ constexpr int tw_stage_off(int N, int RMAX, int s) {
+    int o = 0;
+    for (int i = 1; i < s; ++i) o += tw_stage_size(N, RMAX, i);
+    return o;
+}
+__host__ __device__ constexpr int tw_total(int N, int RMAX) {
+    return tw_stage_off(N, RMAX, sched_nstages(N, RMAX));
+}
+__host__ __device__ constexpr bool uses_tile(int N, int RMAX) { return sched_nstages(N, RMAX) > 1; }
+// LDS elements for a T-line tile, its twiddle tables and (pass 1) two
+// buffers of the inter-pass weight table of T x (E+1) entries.
+__host__ __device__ constexpr int lds_elems(int N, int RMAX, int T, bool epilogue) {
+    return (uses_tile(N, RMAX) ? T * line_pitch(N) + tw_total(N, RMAX) : 0) +
+           (epilogue ? 2 * T * (vals_per_thread(N) + 1) : 0);
+}
 
-template <int N, bool LINE_MINOR> struct LdsMap {
-    __device__ __forceinline__ static int at(int c, int e, int T) {
-        if constexpr (LINE_MINOR) return pad16(e) * T + c;
-        else return c * (N + (N >> 4)) + pad16(e);
+template <int N> __device__ __forceinline__ constexpr int lpad(int e) { return e + (e >> 4); }
+
+// ---------------------------------------------------------------------------
+// Buffer-resource memory access.  Each pass addresses its global data through
+// a buffer descriptor over exactly the bytes the workgroup may touch: one
+// VGPR lane offset serves every slot (the per-slot stride is a scalar), and
+// an access outside the range reads zero / is dropped instead of faulting.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    // Word 3 = 0x00020000: raw (untyped) 32-bit data format on gfx9-class parts.
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), short(0), int(bytes),
+                                             0x00020000);
+}
+__device__ __forceinline__ float2 buf_load(const float2 *, rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ double2 buf_load(const double2 *, rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_store(float2 v, rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+// A 16-byte element is stored as two 8-byte stores: with a single 16-byte
+// buffer store, the compiler here lets the next VALU instruction overwrite
+// the store's first data register without a wait state, and the stored
+// first dword then intermittently holds the new value.
+// (The empty asm statement keeps the two stores from being merged back.)
+__device__ __forceinline__ void buf_store(double2 v, rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v.x), r, voff, soff, 0);
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v.y), r, voff + 8, soff, 0);
+}
+// Element index held by register slot s on entry (first-stage layout) or on
+// exit (last-stage layout) relative to the thread's j: slot i*R + r <->
+// j + i*TPL + r*(N/R).
+template <int N, int R> __device__ __forceinline__ constexpr int slot_off(int s) {
+    return (s / R) * (N / vals_per_thread(N)) + (s % R) * (N / R);
+}
+
+// Fill the stage twiddle tables in LDS from the global table w_N^e (e < N,
+// +1 root).  Every thread of the workgroup takes part; a barrier must follow
+// before the tables are read.
+template <typename C, int N, int RMAX, int STG = 1>
+__device__ __forceinline__ void fill_twiddles(C *twl, const C *__restrict__ tw, int tid, int nthr) {
+    if constexpr (STG < sched_nstages(N, RMAX)) {
+        constexpr int R = sched_radix(N, RMAX, STG), NS = sched_ns(N, RMAX, STG);
+        constexpr int M = NS * R, ROW = R + 1;
+        constexpr int LO = tw_lo_rows(N, RMAX, STG), HI = tw_hi_rows(N, RMAX, STG);
+        constexpr int OFF = tw_stage_off(N, RMAX, STG);
+        for (int i = tid; i < (LO + HI) * ROW; i += nthr) {
+            const int row = i / ROW, r = i - row * ROW;
+            if (r >= R) continue;
+            // LO rows: w_M^(r*row); HI rows: w_M^(16*r*(row-LO)).
+            const int ex = row < LO ? r * row : 16 * r * (row - LO);
+            twl[OFF + i] = tw[ex * (N / M)];
+        }
+        fill_twiddles<C, N, RMAX, STG + 1>(twl, tw, tid, nthr);
     }
-    static constexpr int elems_per_line() { return N + (N >> 4); }
-};
+}
 
-// Run the whole stage schedule on one thread's registers.  On entry v[] holds
-// the stage-0 inputs: slot i*R0 + r = element j + i*TPL + r*(N/R0).  On exit
-// v[] holds the outputs: slot i*RL + r = element j + i*TPL + r*(N/RL), where
-// RL is the last stage's radix.  `tw` is the table w_N^e, e < N (+1 root).
-template <typename C, int N, int RMAX, bool LINE_MINOR, int STG = 0>
-__device__ __forceinline__ void run_stages(C *v, C *lds, int c, int j, int T,
-                                           const C *__restrict__ tw) {
-    using S = Sched<N, RMAX>;
-    using M = LdsMap<N, LINE_MINOR>;
-    constexpr int E = S::E, TPL = S::TPL;
-    constexpr int R = S::radix(STG);
-    constexpr int NS = S::ns(STG);
+// Run the whole stage schedule on one thread's registers.
+//   v      E values; on entry slot i*R0 + r = element j + i*TPL + r*(N/R0),
+//          on exit slot i*RL + r = element j + i*TPL + r*(N/RL).
+//   line   this thread's line in the LDS tile
+//   twl    the LDS twiddle tables
+// The first LDS write happens without a barrier: the caller orders it after
+// any earlier readers of the tile.
+template <typename C, int N, int RMAX, int STG = 0>
+__device__ __forceinline__ void run_stages(C *v, C *line, const C *twl, int j) {
+    constexpr int E = vals_per_thread(N), TPL = N / E;
+    constexpr int NST = sched_nstages(N, RMAX);
+    constexpr int R = sched_radix(N, RMAX, STG);
+    constexpr int NS = sched_ns(N, RMAX, STG);
     constexpr int NB = E / R;
-    if constexpr (STG > 0) {
+    if constexpr (STG > 0 && NS > 1) {
+        constexpr int ROW = R + 1, LO = tw_lo_rows(N, RMAX, STG);
+        constexpr int OFF = tw_stage_off(N, RMAX, STG);
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-            const int b = j + i * TPL;
+            const int k = (j + i * TPL) & (NS - 1);
+            const C *lo = twl + OFF + (k & 15) * ROW;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i * R + r] = lds[M::at(c, b + r * (N / R), T)];
-        }
-        if constexpr (NS > 1) {
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                const int b = j + i * TPL;
-                const int k = b & (NS - 1);
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    const C w = tw[r * k * (N / (NS * R))];
-                    v[i * R + r] = cmulc(v[i * R + r], w);
-                }
+            for (int r = 1; r < R; ++r) {
+                C w = lo[r];
+                if constexpr (NS > 16) w = cmul(w, twl[OFF + (LO + (k >> 4)) * ROW + r]);
+                v[i * R + r] = cmulc(v[i * R + r], w);
             }
         }
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) dft<R>(&v[i * R]);
-    if constexpr (STG + 1 < S::NSTAGES) {
-        if constexpr (STG > 0) __syncthreads();
+    if constexpr (STG + 1 < NST) {
+        constexpr int R2 = sched_radix(N, RMAX, STG + 1), NB2 = E / R2;
+        if constexpr (STG > 0) __syncthreads(); // earlier readers of the tile are done
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int b = j + i * TPL;
             const int base = (b / NS) * NS * R + (b & (NS - 1));
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[M::at(c, base + r * NS, T)] = v[i * R + r];
+            for (int r = 0; r < R; ++r) line[lpad<N>(base + r * NS)] = v[i * R + r];
         }
         __syncthreads();
-        run_stages<C, N, RMAX, LINE_MINOR, STG + 1>(v, lds, c, j, T, tw);
+#pragma unroll
+        for (int i = 0; i < NB2; ++i) {
+            const int b = j + i * TPL;
+#pragma unroll
+            for (int r = 0; r < R2; ++r) v[i * R2 + r] = line[lpad<N>(b + r * (N / R2))];
+        }
+        run_stages<C, N, RMAX, STG + 1>(v, line, twl, j);
     }
-}
-
-// Element index held by register slot s on entry (first stage layout) or on
-// exit (last stage layout): slot i*R + r <-> j + i*TPL + r*(N/R).
-template <int N, int R, int E> __device__ __forceinline__ constexpr int slot_elem_off(int s) {
-    return (s / R) * (N / E) + (s % R) * (N / R);
 }
 
 } // namespace liftfft

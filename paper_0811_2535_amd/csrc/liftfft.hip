@@ -49,109 +49,150 @@ struct PassArgs {
     int64_t lines;     // batch * lines per transform
     int64_t n;         // transform length
     int32_t log2p, log2q;
-    int32_t log2T;  // lines per workgroup of this kernel
-    int32_t log2T1; // lines per workgroup of pass 1 (scratch tile width)
+    int32_t log2T;  // lines per tile of this kernel
+    int32_t log2T1; // lines per tile of pass 1 (scratch tile width)
     int32_t log2h;
     int32_t conj_in, conj_out;
     int32_t xcd_remap;
 };
 
 // Workgroup -> tile.  Workgroups are dispatched round-robin over the 8 XCDs;
-// remapping gives each XCD a contiguous range of tiles, so tiles that share
-// cache lines (adjacent columns in pass 1, adjacent rows in pass 2) are
-// resident in the same L2.
+// with the remap each XCD owns a contiguous range of tiles, so tiles that
+// share cache lines (adjacent columns in pass 1, adjacent rows in pass 2) are
+// in flight in the same L2 at the same time.
 __device__ __forceinline__ int64_t tile_index(int remap) {
     const int64_t bid = blockIdx.x, G = gridDim.x;
-    if (remap) return (bid & 7) * (G >> 3) + (bid >> 3);
+    if (remap) return (bid & 7) * (G >> 3) + (bid >> 3); // G is a multiple of 8
     return bid;
 }
 
-// Largest workgroup per element type: FP64 tiles keep 256 VGPRs per lane.
+// Largest workgroup: 1024 threads for complex64, 512 for complex128 (whose
+// tiles keep up to 256 VGPRs per lane).
 template <typename Real> constexpr int max_threads() { return sizeof(Real) == 4 ? 1024 : 512; }
 
+// One launch of a pass: each workgroup transforms one tile of T consecutive
+// lines.  All data accesses go through buffer descriptors covering exactly
+// the tile's range.
 template <typename Real, int N, int RMAX, int KIND>
 __global__ __launch_bounds__(max_threads<Real>()) void pass_kernel(PassArgs a) {
     using C = typename Cx<Real>::T;
-    using S = Sched<N, RMAX>;
-    constexpr int E = S::E, TPL = S::TPL;
-    constexpr int R0 = S::radix(0), RL = S::radix(S::NSTAGES - 1);
-    constexpr bool LM = (KIND != K_SINGLE);
+    constexpr uint32_t ES = sizeof(C);
+    constexpr int E = vals_per_thread(N), TPL = N / E;
+    constexpr int NST = sched_nstages(N, RMAX);
+    constexpr int R0 = sched_radix(N, RMAX, 0), RL = sched_radix(N, RMAX, NST - 1);
+    constexpr int PITCH = line_pitch(N);
+    constexpr bool TILE = uses_tile(N, RMAX);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
 
-    const int T = 1 << a.log2T;
-    const int tid = threadIdx.x;
-    int c, j;
-    if constexpr (LM) {
-        c = tid & (T - 1);
-        j = tid >> a.log2T;
+    const int log2T = a.log2T, T = 1 << log2T;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    int c, j; // line within the tile, position within the line
+    if constexpr (KIND != K_SINGLE) {
+        c = tid & (T - 1); // lanes sweep the lines first: adjacent columns / rows
+        j = tid >> log2T;
     } else {
-        j = tid & (TPL - 1);
+        j = tid & (TPL - 1); // lanes sweep one contiguous line first
         c = tid / TPL;
     }
-    const int64_t line = tile_index(a.xcd_remap) * T + c;
-    const bool active = line < a.lines;
-
+    const int64_t line0 = tile_index(a.xcd_remap) << log2T; // workgroup-uniform
+    const bool active = line0 + c < a.lines;
+    C *twl = lds + (TILE ? T * PITCH : 0);
+    C *ep = twl + (TILE ? tw_total(N, RMAX) : 0);
+    const Real sin_ = a.conj_in ? Real(-1) : Real(1);
+    const Real sout = a.conj_out ? Real(-1) : Real(1);
     const C *__restrict__ in = static_cast<const C *>(a.in);
     C *__restrict__ out = static_cast<C *>(a.out);
-    const C *__restrict__ tw = static_cast<const C *>(a.tw);
+    const int64_t pmask = (int64_t(1) << a.log2p) - 1, qmask = (int64_t(1) << a.log2q) - 1;
 
+    // 1. Data loads: a buffer descriptor over the tile's range, one 32-bit
+    //    lane offset, and a uniform per-slot offset.
     C v[E];
     if (active) {
-        int64_t base;
         if constexpr (KIND == K_SINGLE) {
-            base = line * N;
-        } else if constexpr (KIND == K_PASS1) {
-            const int64_t b = line >> a.log2p, j1 = line & ((int64_t(1) << a.log2p) - 1);
-            base = b * a.n + j1;
-        } else {
-            const int64_t b = line >> a.log2q, k2 = line & ((int64_t(1) << a.log2q) - 1);
-            base = b * a.n + (k2 << a.log2T1);
-        }
+            const int64_t nl = a.lines - line0 < T ? a.lines - line0 : T;
+            const rsrc_t src = make_rsrc(in + line0 * N, uint32_t(nl * N) * ES);
+            const uint32_t lane = (uint32_t(c) * N + uint32_t(j)) * ES;
 #pragma unroll
-        for (int s = 0; s < E; ++s) {
-            const int e = j + slot_elem_off<N, R0, E>(s);
-            int64_t off;
-            if constexpr (KIND == K_SINGLE) off = e;
-            else if constexpr (KIND == K_PASS1) off = int64_t(e) << a.log2p;           // j2
-            else off = (int64_t(e >> a.log2T1) << (a.log2q + a.log2T1)) +             // j1
-                       (e & ((1 << a.log2T1) - 1));
-            v[s] = conj_if(in[base + off], a.conj_in != 0);
+            for (int s = 0; s < E; ++s)
+                v[s] = scale_im(buf_load(in, src, lane, uint32_t(slot_off<N, R0>(s)) * ES), sin_);
+        } else if constexpr (KIND == K_PASS1) {
+            const int64_t b = line0 >> a.log2p, j10 = line0 & pmask;
+            const rsrc_t src = make_rsrc(in + b * a.n + j10, uint32_t(a.n - j10) * ES);
+            const uint32_t lane = (uint32_t(c) + (uint32_t(j) << a.log2p)) * ES;
+#pragma unroll
+            for (int s = 0; s < E; ++s)
+                v[s] = scale_im(buf_load(in, src, lane, (uint32_t(slot_off<N, R0>(s)) << a.log2p) * ES),
+                                sin_);
+        } else {
+            // Scratch layout S[j1/T1][k2][j1%T1]; the plan keeps T1 | TPL, so
+            // j1 = j + off(s) with off(s) a multiple of T1.
+            const int64_t b = line0 >> a.log2q, k20 = line0 & qmask;
+            const int l2T1 = a.log2T1, T1 = 1 << l2T1;
+            const rsrc_t src = make_rsrc(in + b * a.n + (k20 << l2T1), uint32_t(a.n - (k20 << l2T1)) * ES);
+            const uint32_t lane = ((uint32_t(j >> l2T1) << (a.log2q + l2T1)) + uint32_t(j & (T1 - 1)) +
+                                   (uint32_t(c) << l2T1)) * ES;
+#pragma unroll
+            for (int s = 0; s < E; ++s)
+                v[s] = scale_im(buf_load(in, src, lane, (uint32_t(slot_off<N, R0>(s)) << a.log2q) * ES),
+                                sin_);
         }
     } else {
 #pragma unroll
         for (int s = 0; s < E; ++s) v[s] = mk<C>(Real(0), Real(0));
     }
 
-    run_stages<C, N, RMAX, LM>(v, lds, c, j, T, tw);
-
-    if (!active) return;
-    if constexpr (KIND == K_SINGLE) {
-        const int64_t base = line * N;
-#pragma unroll
-        for (int s = 0; s < E; ++s)
-            out[base + j + slot_elem_off<N, RL, E>(s)] = conj_if(v[s], a.conj_out != 0);
-    } else if constexpr (KIND == K_PASS1) {
+    // 2. Weight tables into LDS (published by the first barrier of the stage
+    //    loop, or the explicit one below when the schedule has one stage).
+    if constexpr (TILE) fill_twiddles<C, N, RMAX>(twl, static_cast<const C *>(a.tw), tid, nthr);
+    C A = mk<C>(Real(1), Real(0));
+    if constexpr (KIND == K_PASS1) {
+        // Inter-pass weight w_n^(-j1*k2) with k2 = j + off(s): w_n^(j1*j)
+        // (per thread) times P[c][s] = w_n^(j1*off(s)) (per line, in LDS),
+        // both from the two-level FP64-generated tables.
         const C *__restrict__ hi = static_cast<const C *>(a.tw_hi);
         const C *__restrict__ lo = static_cast<const C *>(a.tw_lo);
-        const int64_t b = line >> a.log2p, j1 = line & ((int64_t(1) << a.log2p) - 1);
-        const int64_t base = b * a.n + ((j1 >> a.log2T) << (a.log2q + a.log2T)) + (j1 & (T - 1));
-        const int64_t lomask = (int64_t(1) << a.log2h) - 1;
-#pragma unroll
-        for (int s = 0; s < E; ++s) {
-            const int k2 = j + slot_elem_off<N, RL, E>(s);
-            const int64_t ex = j1 * k2; // < n: no reduction needed
-            const C w = cmul(hi[ex >> a.log2h], lo[ex & lomask]);
-            out[base + (int64_t(k2) << a.log2T)] = cmulc(v[s], w);
+        const int lomask = (1 << a.log2h) - 1;
+        const int j10 = int(line0 & pmask);
+        const int xa = (j10 + c) * j;
+        A = cmul(hi[xa >> a.log2h], lo[xa & lomask]);
+        for (int i = tid; i < T * (E + 1); i += nthr) {
+            const int cc = i / (E + 1), s = i - cc * (E + 1);
+            if (s >= E) continue;
+            const int off = (s / RL) * TPL + (s % RL) * (N / RL);
+            const int x = (j10 + cc) * off;
+            ep[i] = cmul(hi[x >> a.log2h], lo[x & lomask]);
         }
+        if constexpr (!TILE) __syncthreads();
+    }
+
+    run_stages<C, N, RMAX>(v, lds + c * PITCH, twl, j);
+
+    // 3. Stores.
+    if (!active) return;
+    if constexpr (KIND == K_SINGLE) {
+        const int64_t nl = a.lines - line0 < T ? a.lines - line0 : T;
+        const rsrc_t dst = make_rsrc(out + line0 * N, uint32_t(nl * N) * ES);
+        const uint32_t lane = (uint32_t(c) * N + uint32_t(j)) * ES;
+#pragma unroll
+        for (int s = 0; s < E; ++s)
+            buf_store(scale_im(v[s], sout), dst, lane, uint32_t(slot_off<N, RL>(s)) * ES);
+    } else if constexpr (KIND == K_PASS1) {
+        // Tile j1/T of the scratch array S[j1/T][k2][j1%T].
+        const int64_t b = line0 >> a.log2p, j10 = line0 & pmask;
+        const rsrc_t dst = make_rsrc(out + b * a.n + (j10 << a.log2q), uint32_t(T << a.log2q) * ES);
+        const uint32_t lane = ((uint32_t(j) << log2T) + uint32_t(c)) * ES;
+        const C *P = ep + c * (E + 1);
+#pragma unroll
+        for (int s = 0; s < E; ++s)
+            buf_store(cmulc(v[s], cmul(A, P[s])), dst, lane, (uint32_t(slot_off<N, RL>(s)) << log2T) * ES);
     } else {
-        const int64_t b = line >> a.log2q, k2 = line & ((int64_t(1) << a.log2q) - 1);
-        const int64_t base = b * a.n + k2;
+        const int64_t b = line0 >> a.log2q, k20 = line0 & qmask;
+        const rsrc_t dst = make_rsrc(out + b * a.n + k20, uint32_t(a.n - k20) * ES);
+        const uint32_t lane = (uint32_t(c) + (uint32_t(j) << a.log2q)) * ES;
 #pragma unroll
-        for (int s = 0; s < E; ++s) {
-            const int k1 = j + slot_elem_off<N, RL, E>(s);
-            out[base + (int64_t(k1) << a.log2q)] = conj_if(v[s], a.conj_out != 0);
-        }
+        for (int s = 0; s < E; ++s)
+            buf_store(scale_im(v[s], sout), dst, lane, (uint32_t(slot_off<N, RL>(s)) << a.log2q) * ES);
     }
 }
 
@@ -213,7 +254,7 @@ int ilog2_exact(int64_t v) {
 struct Launch {
     KernelFn fn = nullptr;
     int log2N = 0, log2T = 0;
-    int64_t lines = 0, blocks = 0;
+    int64_t lines = 0, ntiles = 0, grid = 0;
     int threads = 0;
     size_t lds = 0;
     bool remap = false;
@@ -243,45 +284,62 @@ struct fft_plan {
 
 namespace {
 
-// Lines per workgroup: the largest power of two T <= max_lines with
-// T * threads_per_line <= 1024 and T tiles within the LDS budget, stopping
-// once the tile has `want_threads` threads and at least `min_T` lines.
-// `cap` (0 = none) bounds T from above.
-// A line needs LDS when its schedule has more than one stage, i.e. when it is
-// longer than the largest radix that fits in one thread's registers.
-bool needs_lds(int64_t N, int rmax) { return N > (rmax < 16 ? rmax : 16); }
-
+// Lines per tile: the smallest power of two T <= max_lines whose tile has at
+// least `want_threads` threads and `min_T` lines, as long as it fits the
+// thread and LDS limits; `cap` (0 = none) bounds T.
 int choose_log2T(int log2N, int rmax, size_t esize, int64_t max_lines, int want_threads,
-                 int min_T, int cap) {
+                 int min_T, int cap, bool epilogue) {
     const int64_t thread_cap = esize == 8 ? max_threads<float>() : max_threads<double>();
-    const int64_t N = int64_t(1) << log2N;
-    const int64_t tpl = N / (N < 16 ? N : 16);
-    const int64_t per_line = (N + N / 16) * int64_t(esize);
+    const int N = 1 << log2N;
+    const int64_t tpl = N / vals_per_thread(N);
+    auto fits = [&](int64_t T) {
+        return T <= max_lines && T * tpl <= thread_cap &&
+               int64_t(lds_elems(N, rmax, int(T), epilogue)) * int64_t(esize) <= LDS_BUDGET &&
+               (!cap || T <= cap);
+    };
     int log2T = 0;
     for (;;) {
         const int64_t T = int64_t(1) << log2T;
         if (T * tpl >= want_threads && T >= min_T) break;
-        const int64_t T2 = 2 * T;
-        if (T2 > max_lines || T2 * tpl > thread_cap) break;
-        if (needs_lds(N, rmax) && T2 * per_line > LDS_BUDGET - 1024) break;
-        if (cap && T2 > cap) break;
+        if (!fits(2 * T)) break;
         ++log2T;
     }
     return log2T;
 }
 
-void fill_launch(Launch &L, int dtype, int kind, int log2N, int rmax, int log2T, int64_t lines) {
-    const int64_t N = int64_t(1) << log2N;
-    const int64_t E = N < 16 ? N : 16;
+// Fill a launch description: tile shape, LDS and grid (one workgroup per
+// tile).
+bool fill_launch(Launch &L, int dtype, int kind, int log2N, int rmax, int log2T, int64_t lines) {
+    const int N = 1 << log2N;
     const size_t esize = dtype == FFT_C64 ? 8 : 16;
     L.fn = pick_kernel(dtype, kind, log2N, rmax);
+    if (!L.fn) return false;
     L.log2N = log2N;
     L.log2T = log2T;
     L.lines = lines;
-    L.threads = int((N / E) << log2T);
-    L.blocks = (lines + (int64_t(1) << log2T) - 1) >> log2T;
-    L.lds = needs_lds(N, rmax) ? size_t((N + N / 16) << log2T) * esize : 0;
-    L.remap = (L.blocks % 8 == 0) && L.blocks >= 16;
+    L.threads = (N / vals_per_thread(N)) << log2T;
+    L.ntiles = (lines + (int64_t(1) << log2T) - 1) >> log2T;
+    L.grid = L.ntiles;
+    L.lds = size_t(lds_elems(N, rmax, 1 << log2T, kind == K_PASS1)) * esize;
+    if (L.lds > 65536 &&
+        hipFuncSetAttribute(reinterpret_cast<const void *>(L.fn),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(L.lds)) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    L.remap = (L.grid % 8 == 0) && L.grid >= 16;
+    return L.grid <= INT32_MAX;
+}
+
+// Tile shape for a pass kernel: pass 1 aims at 512-thread tiles of at least
+// two lines (two workgroups per CU), pass 2 at tiles of at least four lines
+// (32-byte segments in the natural-order output), both capped by `cap`.
+bool plan_pass(Launch &L, int dtype, int kind, int log2N, int rmax, int64_t lines_per_transform,
+               int64_t lines, int cap) {
+    const size_t esize = dtype == FFT_C64 ? 8 : 16;
+    const bool p1 = kind == K_PASS1;
+    const int l2T = choose_log2T(log2N, rmax, esize, lines_per_transform, 512, p1 ? 2 : 4, cap, p1);
+    return fill_launch(L, dtype, kind, log2N, rmax, l2T, lines);
 }
 
 int gen_table(int dtype, void *dst, int64_t count, int64_t mult, int log2N) {
@@ -336,8 +394,8 @@ void free_plan(fft_plan *p) {
 }
 
 int launch(const fft_plan *p, const Launch &L, const PassArgs &args, hipStream_t st) {
-    if (L.blocks <= 0) return FFT_OK;
-    hipLaunchKernelGGL(L.fn, dim3(unsigned(L.blocks)), dim3(unsigned(L.threads)), L.lds, st, args);
+    if (L.grid <= 0) return FFT_OK;
+    hipLaunchKernelGGL(L.fn, dim3(unsigned(L.grid)), dim3(unsigned(L.threads)), L.lds, st, args);
     (void)p;
     return hipGetLastError() == hipSuccess ? FFT_OK : FFT_E_HIP;
 }
@@ -388,6 +446,8 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
     }
     if (o.log2_p < 0 || (o.log2_p && o.log2_p >= t)) return FFT_E_ARG;
     if (o.lines_per_block < 0 || (o.lines_per_block & (o.lines_per_block - 1))) return FFT_E_ARG;
+    if (o.lines_per_block2 < 0 || (o.lines_per_block2 & (o.lines_per_block2 - 1))) return FFT_E_ARG;
+    if (o.flags & ~int32_t(FFT_OPT_NO_XCD_REMAP)) return FFT_E_ARG;
 
     fft_plan *p = new (std::nothrow) fft_plan;
     if (!p) return FFT_E_OOM;
@@ -398,6 +458,7 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
     p->radix = radix;
     p->esize = esize;
     if (hipGetDevice(&p->device) != hipSuccess) {
+        (void)hipGetLastError();
         free_plan(p);
         return FFT_E_HIP;
     }
@@ -405,8 +466,11 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
     if (o.log2_p == 0 && t <= MAX_LOG2_LINE) {
         p->passes = 1;
         p->log2q = t;
-        const int l2T = choose_log2T(t, radix, esize, batch, 256, 1, o.lines_per_block);
-        fill_launch(p->k1, dtype, K_SINGLE, t, radix, l2T, batch);
+        const int l2T = choose_log2T(t, radix, esize, batch, 256, 1, o.lines_per_block, false);
+        if (!fill_launch(p->k1, dtype, K_SINGLE, t, radix, l2T, batch)) {
+            free_plan(p);
+            return FFT_E_UNSUPPORTED;
+        }
     } else {
         p->passes = 2;
         p->log2q = o.log2_p ? t - o.log2_p : (t + 1) / 2;
@@ -416,11 +480,17 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
             return FFT_E_UNSUPPORTED;
         }
         const int64_t P = int64_t(1) << p->log2p, Q = int64_t(1) << p->log2q;
-        const int l2T1 = choose_log2T(p->log2q, radix, esize, P, 256, 4, o.lines_per_block);
-        const int l2T2 = choose_log2T(p->log2p, radix, esize, Q, 256, 4, 0);
-        fill_launch(p->k1, dtype, K_PASS1, p->log2q, radix, l2T1, P * batch);
-        fill_launch(p->k2, dtype, K_PASS2, p->log2p, radix, l2T2, Q * batch);
+        // Pass 2 reads the scratch tile layout of pass 1 with a separable
+        // offset, which needs T1 | TPL2 (TPL2 = threads per pass-2 line).
+        const int tpl2 = int(P / vals_per_thread(int(P)));
+        const int cap1 = o.lines_per_block ? (o.lines_per_block < tpl2 ? o.lines_per_block : tpl2) : tpl2;
+        if (!plan_pass(p->k1, dtype, K_PASS1, p->log2q, radix, P, P * batch, cap1) ||
+            !plan_pass(p->k2, dtype, K_PASS2, p->log2p, radix, Q, Q * batch, o.lines_per_block2)) {
+            free_plan(p);
+            return FFT_E_UNSUPPORTED;
+        }
     }
+    if (o.flags & FFT_OPT_NO_XCD_REMAP) p->k1.remap = p->k2.remap = false;
     if (!p->k1.fn || (p->passes == 2 && !p->k2.fn)) {
         free_plan(p);
         return FFT_E_UNSUPPORTED;
@@ -462,15 +532,6 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
         if (rc == FFT_OK) rc = gen_table(dtype, tl, nlo, 1, t);
     }
     if (rc == FFT_OK && hipDeviceSynchronize() != hipSuccess) rc = FFT_E_HIP;
-    // Allow the large LDS tiles (above the 64 KiB default) for these kernels.
-    for (Launch *L : {&p->k1, &p->k2}) {
-        if (rc != FFT_OK || !L->fn || L->lds <= 65536) continue;
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(L->fn),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                int(L->lds)) != hipSuccess) {
-            (void)hipGetLastError();
-        }
-    }
     if (rc != FFT_OK) {
         free_plan(p);
         return rc;
@@ -579,6 +640,12 @@ int fft_plan_get_info(const fft_plan *p, fft_plan_info *info) {
     info->radix = p->radix;
     info->lines_per_block_pass1 = 1 << p->k1.log2T;
     info->lines_per_block_pass2 = p->passes == 2 ? (1 << p->k2.log2T) : 0;
+    info->grid_pass1 = int32_t(p->k1.grid);
+    info->grid_pass2 = p->passes == 2 ? int32_t(p->k2.grid) : 0;
+    info->threads_pass1 = p->k1.threads;
+    info->threads_pass2 = p->passes == 2 ? p->k2.threads : 0;
+    info->lds_bytes_pass1 = int64_t(p->k1.lds);
+    info->lds_bytes_pass2 = p->passes == 2 ? int64_t(p->k2.lds) : 0;
     info->scratch_bytes = int64_t(p->scratch_bytes);
     info->table_bytes = int64_t(p->table_bytes);
     return FFT_OK;

@@ -74,8 +74,12 @@ def test_create_rejects_bad_options():
              (PlanOpts(-1, 0, 0), -9), (PlanOpts(0, 0, 3), -9), (PlanOpts(0, 32, 0), -9)]
     for opts, want in cases:
         assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(opts), ctypes.byref(h)) == want
-    bad = PlanOpts(0, 0, 0)
+    bad = PlanOpts(0, 0, 0, 0, 0)
     bad.reserved[2] = 1
+    assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(PlanOpts(0, 0, 0, 3, 0)),
+                                ctypes.byref(h)) == -9
+    assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(PlanOpts(0, 0, 0, 0, 6)),
+                                ctypes.byref(h)) == -9
     assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(bad), ctypes.byref(h)) == -9
     assert L.fft_plan_create(1024, 1, 0, None) == -4
 

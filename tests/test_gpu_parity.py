@@ -28,25 +28,41 @@ def lf(torch):
     return lf
 
 
-def run_plan(lf, x_np, sign, **opts):
-    """Execute one plan over the rows of x_np (batch, n) and return numpy."""
+def run_plan(lf, x_np, sign, repeat=1, **opts):
+    """Execute one plan over the rows of x_np (batch, n) and return numpy
+    (with repeat > 1, a list of the outputs of repeated executions)."""
     import torch
     batch, n = x_np.shape
     dt = torch.complex64 if x_np.dtype == np.complex64 else torch.complex128
     plan = lf.Plan(n, batch, dt, **opts)
     x = to_dev(x_np)
-    y = torch.empty_like(x)
-    plan.execute(x, y, sign)
-    torch.cuda.synchronize()
-    out = to_np(y)
+    outs = []
+    for _ in range(repeat):
+        y = torch.full_like(x, float("nan"))
+        plan.execute(x, y, sign)
+        torch.cuda.synchronize()
+        outs.append(to_np(y))
     plan.destroy()
-    return out
+    return outs[0] if repeat == 1 else outs
+
+
+def mismatch_report(got, x_np, sign, ref):
+    """Where the GPU result and the oracle disagree, and whether numpy agrees
+    with the oracle (to tell an oracle fault from a GPU one)."""
+    npref = np.fft.fft(x_np.astype(np.complex128), axis=1) if sign < 0 else \
+        x_np.shape[1] * np.fft.ifft(x_np.astype(np.complex128), axis=1)
+    d = np.abs(got - ref)
+    big = d > 1e-3 * np.abs(ref).max()
+    return dict(gpu_vs_numpy=[oracle.rel_l2(got[b], npref[b]) for b in range(len(got))],
+                oracle_vs_numpy=[oracle.rel_l2(ref[b], npref[b]) for b in range(len(got))],
+                n_far=int(big.sum()), worst=np.unravel_index(int(np.argmax(d)), d.shape),
+                nan=int(np.isnan(got).sum()))
 
 
 def check_rows(got, x_np, sign, tol):
     ref = oracle.fft_batch(x_np.astype(np.complex128), sign)
     errs = [oracle.rel_l2(got[b], ref[b]) for b in range(x_np.shape[0])]
-    assert max(errs) <= tol, (max(errs), tol)
+    assert max(errs) <= tol, (errs, tol, mismatch_report(got, x_np, sign, ref))
     return max(errs)
 
 
