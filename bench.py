@@ -32,7 +32,7 @@ if ROOT not in sys.path:
 METRIC = ("GFLOP/s (5n·log2n) + HBM GB/s % peak, c64 n=2^24; fwd+bwd and batched "
           "vs plain")
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c64_n2p24.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c64_n2p24.txt")
 
 
 def kernel_source_hash() -> str:
@@ -57,6 +57,63 @@ def load_traffic(kernel: str, launches_bytes: float):
     if not k:
         return None
     return k.get("hbm_bytes_per_launch")
+
+
+def _kernel_role(name: str) -> str | None:
+    if "pass_kernel<float, 4096, 16, 1>" in name:
+        return "pass1"
+    if "pass_kernel<float, 4096, 16, 2>" in name:
+        return "pass2"
+    if "neg" in name:
+        return "reference"
+    return None
+
+
+def summarize_counters(fetch_csv: str, write_csv: str, log2n: int, out_path: str) -> dict:
+    """HBM traffic per launch of each pass from two rocprofv3 --pmc runs of this
+    benchmark (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by
+    what the same counter reads for the reference streaming kernel, which reads
+    8n and writes 8n bytes."""
+    import csv
+    import statistics
+
+    def per_role(path, counter):
+        vals = {}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row["Counter_Name"] != counter:
+                    continue
+                role = _kernel_role(row["Kernel_Name"])
+                if role:
+                    vals.setdefault(role, []).append(float(row["Counter_Value"]) * 1024.0)
+        return {k: statistics.mean(v) for k, v in vals.items()}, {k: len(v) for k, v in vals.items()}
+
+    n = 1 << log2n
+    known = 8.0 * n
+    fetch, nf = per_role(fetch_csv, "FETCH_SIZE")
+    write, nw = per_role(write_csv, "WRITE_SIZE")
+    f_fac, w_fac = known / fetch["reference"], known / write["reference"]
+    bargs = "--steps 2 --warmup 1 --sets 4 --copy-reps 3 --no-cpu-baseline"
+    rec = {"source_hash": kernel_source_hash(), "log2n": log2n,
+           "commands": [
+               "timeout -s KILL 60 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch "
+               "-o run -- python3 bench.py " + bargs,
+               "timeout -s KILL 60 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write "
+               "-o run -- python3 bench.py " + bargs,
+               "python3 bench.py --summarize-counters gpurun_out/pmc_fetch/run_counter_collection.csv "
+               "gpurun_out/pmc_write/run_counter_collection.csv"],
+           "reference": {"fetch_counter_bytes": fetch["reference"], "write_counter_bytes": write["reference"],
+                         "fetch_scale": f_fac, "write_scale": w_fac, "bytes_each_way": known},
+           "kernels": {}}
+    for role in ("pass1", "pass2"):
+        fb, wb = fetch[role] * f_fac, write[role] * w_fac
+        rec["kernels"][role] = {"fetch_bytes": fb, "write_bytes": wb, "hbm_bytes_per_launch": fb + wb,
+                                "ratio_to_algorithmic": (fb + wb) / (2 * known),
+                                "dispatches": [nf.get(role, 0), nw.get(role, 0)]}
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    return rec
 
 
 def cpu_baseline(x0, x1, y0_gpu, y1_gpu):
@@ -89,10 +146,19 @@ def main() -> int:
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--sets", type=int, default=4, help="buffer sets rotated between transforms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic summary from two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) of this benchmark and exit")
     ap.add_argument("--copy-reps", type=int, default=10,
                     help="device-to-device copies of one pass's bytes, timed for context and "
                          "used as the known-size reference kernel for HBM counters")
     args = ap.parse_args()
+
+    if args.summarize_counters:
+        rec = summarize_counters(args.summarize_counters[0], args.summarize_counters[1], args.log2n,
+                                 TRAFFIC_FILE)
+        print(json.dumps(rec))
+        return 0
 
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported "
