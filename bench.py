@@ -276,6 +276,7 @@ def main() -> int:
             "n": n, "batch": 1, "passes": info["passes"], "log2_p": info["log2_p"],
             "log2_q": info["log2_q"], "radix": info["radix"],
             "lines_per_block": [info["lines_per_block_pass1"], info["lines_per_block_pass2"]],
+            "kernel_variants": [info["variant_pass1"], info["variant_pass2"]],
         },
         "hbm": {
             "alg_bytes_per_step": alg_bytes_step,

@@ -90,17 +90,44 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out);
  *   lines_per_block   lines (independent short transforms) per workgroup in
  *                     pass 1, or in the single pass (0 = default; power of two).
  *   lines_per_block2  lines per workgroup in pass 2 (0 = default; power of two).
+ *                     A tile width that does not fit the kernel's thread or
+ *                     LDS limits, exceeds the lines of one transform, or (pass
+ *                     1) exceeds the threads of one pass-2 line returns
+ *                     FFT_E_UNSUPPORTED.
  *   flags             FFT_OPT_NO_XCD_REMAP: keep the hardware workgroup order
  *                     instead of giving each XCD a contiguous range of tiles.
+ *                     FFT_OPT_SPLIT_EXCHANGE / FFT_OPT_FULL_EXCHANGE: exchange
+ *                     data between stages through LDS one real component at
+ *                     a time (half the LDS per tile) / as complex elements.
+ *                     FFT_OPT_PERSISTENT / FFT_OPT_ONE_TILE: pass kernels run
+ *                     as many workgroups as are resident, each transforming
+ *                     a sequence of tiles with the next tile's loads in
+ *                     flight / one workgroup per tile.
+ *                     FFT_OPT_DENSE: pass kernels capped at 64 VGPRs so that
+ *                     two 1024-thread workgroups fit one CU (16 values per
+ *                     thread, one tile per workgroup only).
+ *   values_per_thread complex values each thread holds in the pass kernels:
+ *                     0 (default), 16 or 32.
+ * Kernel variants other than the defaults exist for complex64 two-pass
+ * plans with radix 16 and pass lines of 2^10..2^12; asking for one elsewhere
+ * returns FFT_E_UNSUPPORTED.  Contradictory flags return FFT_E_ARG.
  */
-enum { FFT_OPT_NO_XCD_REMAP = 1 };
+enum {
+    FFT_OPT_NO_XCD_REMAP = 1,
+    FFT_OPT_SPLIT_EXCHANGE = 2,
+    FFT_OPT_FULL_EXCHANGE = 4,
+    FFT_OPT_PERSISTENT = 8,
+    FFT_OPT_ONE_TILE = 16,
+    FFT_OPT_DENSE = 32
+};
 typedef struct fft_plan_opts {
     int32_t log2_p;
     int32_t radix;
     int32_t lines_per_block;
     int32_t lines_per_block2;
     int32_t flags;
-    int32_t reserved[3];
+    int32_t values_per_thread;
+    int32_t reserved[2];
 } fft_plan_opts;
 
 /* As fft_plan_create with explicit options (opts may be NULL). */
@@ -137,6 +164,9 @@ const char *fft_strerror(int code);
  *   threads_pass1/2            workgroup size
  *   lds_bytes_pass1/2          dynamic LDS per workgroup
  *   scratch_bytes, table_bytes device memory the plan owns
+ *   variant_pass1/2            kernel variant bits: 1 = 32 values per
+ *                              thread, 2 = split exchange, 4 = persistent,
+ *                              8 = dense (64-VGPR cap)
  * Pass-2 fields are 0 for single-pass plans.
  */
 typedef struct fft_plan_info {
@@ -147,6 +177,7 @@ typedef struct fft_plan_info {
     int32_t threads_pass1, threads_pass2;
     int64_t lds_bytes_pass1, lds_bytes_pass2;
     int64_t scratch_bytes, table_bytes;
+    int32_t variant_pass1, variant_pass2;
 } fft_plan_info;
 
 int fft_plan_get_info(const fft_plan *plan, fft_plan_info *info);
@@ -163,7 +194,7 @@ int fft_plan_read_timing(fft_plan *plan, double ms_out[2], int64_t launches_out[
                          int reset);
 
 /* ABI version of this header (major*100 + minor). */
-#define LIFTFFT_ABI_VERSION 100
+#define LIFTFFT_ABI_VERSION 101
 int fft_abi_version(void);
 
 #ifdef __cplusplus

@@ -43,10 +43,19 @@ class FFTError(RuntimeError):
         super().__init__("%s: %s (%s)" % (what, strerror(code), self.name))
 
 
+FFT_OPT_NO_XCD_REMAP = 1
+FFT_OPT_SPLIT_EXCHANGE = 2
+FFT_OPT_FULL_EXCHANGE = 4
+FFT_OPT_PERSISTENT = 8
+FFT_OPT_ONE_TILE = 16
+FFT_OPT_DENSE = 32
+
+
 class PlanOpts(ctypes.Structure):
     _fields_ = [("log2_p", ctypes.c_int32), ("radix", ctypes.c_int32),
                 ("lines_per_block", ctypes.c_int32), ("lines_per_block2", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("flags", ctypes.c_int32), ("values_per_thread", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -58,7 +67,8 @@ class PlanInfo(ctypes.Structure):
                 ("grid_pass1", ctypes.c_int32), ("grid_pass2", ctypes.c_int32),
                 ("threads_pass1", ctypes.c_int32), ("threads_pass2", ctypes.c_int32),
                 ("lds_bytes_pass1", ctypes.c_int64), ("lds_bytes_pass2", ctypes.c_int64),
-                ("scratch_bytes", ctypes.c_int64), ("table_bytes", ctypes.c_int64)]
+                ("scratch_bytes", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
+                ("variant_pass1", ctypes.c_int32), ("variant_pass2", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -127,13 +137,13 @@ class Plan:
 
     def __init__(self, n: int, batch: int = 1, dtype=torch.complex64, log2_p: int = 0,
                  radix: int = 0, lines_per_block: int = 0, lines_per_block2: int = 0,
-                 flags: int = 0):
+                 flags: int = 0, values_per_thread: int = 0):
         self._h = ctypes.c_void_p()
         self.n, self.batch = int(n), int(batch)
         self.dtype_code = dtype_code(dtype)
         self.torch_dtype = torch.complex64 if self.dtype_code == FFT_C64 else torch.complex128
         opts = PlanOpts(int(log2_p), int(radix), int(lines_per_block), int(lines_per_block2),
-                        int(flags))
+                        int(flags), int(values_per_thread))
         rc = lib().fft_plan_create_ex(self.n, self.batch, self.dtype_code, ctypes.byref(opts),
                                       ctypes.byref(self._h))
         _check(rc, "fft_plan_create_ex(n=%d, batch=%d)" % (self.n, self.batch))

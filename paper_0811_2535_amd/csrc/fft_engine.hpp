@@ -3,8 +3,8 @@
 // pass kernel.
 //
 // A workgroup owns T "lines" (independent N-point transforms).  Each line is
-// processed by TPL = N/E threads holding E = min(16, N) complex values in
-// registers.  The stage loop is the paper's stage loop (Section 2.1, Fig. 2.1:
+// processed by TPL = N/E threads holding E = min(EMAX, N) complex values in
+// registers (EMAX = 16 or 32).  The stage loop is the paper's stage loop (Section 2.1, Fig. 2.1:
 // one butterfly stage per doubling of the column length) regrouped into
 // radix-R stages, R <= 16: a radix-R stage is log2(R) radix-2 stages done at
 // once in registers -- the same dimension lifting the paper applies between
@@ -159,7 +159,7 @@ template <int R, typename C> __device__ __forceinline__ void dft(C *v) {
 // remainder, placed second so that the first and last stages (the ones that
 // touch global memory) use the full radix.
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
-__host__ __device__ constexpr int vals_per_thread(int N) { return N < 16 ? N : 16; }
+__host__ __device__ constexpr int vals_per_thread(int N, int EMAX = 16) { return N < EMAX ? N : EMAX; }
 __host__ __device__ constexpr int sched_logr(int N, int RMAX) { return ilog2c(RMAX < N ? RMAX : N); }
 __host__ __device__ constexpr int sched_nstages(int N, int RMAX) {
     return ilog2c(N) / sched_logr(N, RMAX) + (ilog2c(N) % sched_logr(N, RMAX) ? 1 : 0);
@@ -174,13 +174,14 @@ __host__ __device__ constexpr int sched_ns(int N, int RMAX, int s) {
     return p;
 }
 
-// Tile: line c occupies [c*PITCH, c*PITCH + N + N/16); element e sits at
-// e + e/16 within its line (one spare slot per 16 elements spreads the
-// strided Stockham writes over the banks), and the pitch is 8 (mod 32)
-// elements so that the lines of one wavefront start in different banks.
-__host__ __device__ constexpr int line_pitch(int N) {
-    return (N + N / 16) + ((8 - (N + N / 16) % 32) + 32) % 32;
-}
+// Tile: line c occupies [c*pitch, c*pitch + N + N/16) of the exchange array;
+// element e sits at e + e/16 within its line (one spare slot per 16 elements
+// spreads the strided Stockham writes over the banks).  The exchange array
+// holds complex elements, or -- in the split form -- one real component at a
+// time (half the LDS; each exchange then runs twice, real parts first).  The
+// pitch is chosen on the host (exchange_pitch) so that the lines that share a
+// wavefront start in different banks.
+__host__ __device__ constexpr int padded_line(int N) { return N + N / 16; }
 // Stage twiddles w_M^(r*k), M = Ns*R, k < Ns, r < R: with k = klo + 16*khi,
 // w_M^(r*k) = LO[klo][r] * HI[khi][r], LO[klo][r] = w_M^(r*klo) (klo < 16),
 // HI[khi][r] = w_{M/16}^(r*khi) (khi < Ns/16).  Rows padded to R+1 entries.
@@ -202,11 +203,35 @@ __host__ __device__ constexpr int tw_total(int N, int RMAX) {
     return tw_stage_off(N, RMAX, sched_nstages(N, RMAX));
 }
 __host__ __device__ constexpr bool uses_tile(int N, int RMAX) { return sched_nstages(N, RMAX) > 1; }
-// LDS elements for a T-line tile, its twiddle tables and (pass 1) two
-// buffers of the inter-pass weight table of T x (E+1) entries.
-__host__ __device__ constexpr int lds_elems(int N, int RMAX, int T, bool epilogue) {
-    return (uses_tile(N, RMAX) ? T * line_pitch(N) + tw_total(N, RMAX) : 0) +
-           (epilogue ? 2 * T * (vals_per_thread(N) + 1) : 0);
+
+// Line pitch (in exchange elements of `esize` bytes) for a tile of T lines.
+// LDS serves one 128-byte bank window per cycle; in the pass kernels the
+// lanes of a wavefront sweep the T lines first, so line c is shifted by
+// c * 128/T bytes within the window.  In the single-pass kernel
+// (`lines_first` = false) the lanes sweep TPL positions of one line first,
+// and consecutive lines are shifted by TPL elements.
+inline int exchange_pitch(int N, int T, int TPL, int esize, bool lines_first) {
+    const int window = 128 / esize; // exchange elements per bank window
+    int target;
+    if (lines_first) target = T >= window ? 1 : window / T;
+    else target = TPL >= window ? 0 : TPL;
+    int p = padded_line(N);
+    while (p % window != target % window) ++p;
+    return p;
+}
+
+// Byte offsets of the LDS regions of one workgroup: the exchange tile of T
+// lines, the stage twiddle tables (16-byte aligned) and, in pass 1, two
+// buffers of the inter-pass weight table of T x (E+1) entries (alternate
+// tiles of a persistent workgroup use alternate buffers).
+__host__ __device__ constexpr int64_t lds_tile_bytes(int N, int RMAX, int T, int pitch, int lsize) {
+    return uses_tile(N, RMAX) ? ((int64_t(T) * pitch * lsize + 15) & ~int64_t(15)) : 0;
+}
+__host__ __device__ constexpr int64_t lds_ep_offset(int N, int RMAX, int T, int pitch, int lsize, int csize) {
+    return lds_tile_bytes(N, RMAX, T, pitch, lsize) + (uses_tile(N, RMAX) ? int64_t(tw_total(N, RMAX)) * csize : 0);
+}
+inline int64_t lds_bytes(int N, int RMAX, int T, int E, int pitch, int lsize, int csize, bool epilogue) {
+    return lds_ep_offset(N, RMAX, T, pitch, lsize, csize) + (epilogue ? 2 * int64_t(T) * (E + 1) * csize : 0);
 }
 
 template <int N> __device__ __forceinline__ constexpr int lpad(int e) { return e + (e >> 4); }
@@ -246,9 +271,9 @@ __device__ __forceinline__ void buf_store(double2 v, rsrc_t r, uint32_t voff, ui
 }
 // Element index held by register slot s on entry (first-stage layout) or on
 // exit (last-stage layout) relative to the thread's j: slot i*R + r <->
-// j + i*TPL + r*(N/R).
-template <int N, int R> __device__ __forceinline__ constexpr int slot_off(int s) {
-    return (s / R) * (N / vals_per_thread(N)) + (s % R) * (N / R);
+// j + i*TPL + r*(N/R), TPL = N/E.
+template <int N, int E, int R> __device__ __forceinline__ constexpr int slot_off(int s) {
+    return (s / R) * (N / E) + (s % R) * (N / R);
 }
 
 // Fill the stage twiddle tables in LDS from the global table w_N^e (e < N,
@@ -275,13 +300,15 @@ __device__ __forceinline__ void fill_twiddles(C *twl, const C *__restrict__ tw, 
 // Run the whole stage schedule on one thread's registers.
 //   v      E values; on entry slot i*R0 + r = element j + i*TPL + r*(N/R0),
 //          on exit slot i*RL + r = element j + i*TPL + r*(N/RL).
-//   line   this thread's line in the LDS tile
+//   line   this thread's line in the LDS exchange array: complex elements,
+//          or (SPLIT) one real component at a time
 //   twl    the LDS twiddle tables
 // The first LDS write happens without a barrier: the caller orders it after
 // any earlier readers of the tile.
-template <typename C, int N, int RMAX, int STG = 0>
-__device__ __forceinline__ void run_stages(C *v, C *line, const C *twl, int j) {
-    constexpr int E = vals_per_thread(N), TPL = N / E;
+template <typename C, int N, int RMAX, int E, bool SPLIT, int STG = 0>
+__device__ __forceinline__ void run_stages(C *v, void *line_base, const C *twl, int j) {
+    using Real = decltype(C::x);
+    constexpr int TPL = N / E;
     constexpr int NST = sched_nstages(N, RMAX);
     constexpr int R = sched_radix(N, RMAX, STG);
     constexpr int NS = sched_ns(N, RMAX, STG);
@@ -305,22 +332,52 @@ __device__ __forceinline__ void run_stages(C *v, C *line, const C *twl, int j) {
     for (int i = 0; i < NB; ++i) dft<R>(&v[i * R]);
     if constexpr (STG + 1 < NST) {
         constexpr int R2 = sched_radix(N, RMAX, STG + 1), NB2 = E / R2;
-        if constexpr (STG > 0) __syncthreads(); // earlier readers of the tile are done
+        if constexpr (!SPLIT) {
+            C *line = static_cast<C *>(line_base);
+            if constexpr (STG > 0) __syncthreads(); // earlier readers of the tile are done
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            const int b = j + i * TPL;
-            const int base = (b / NS) * NS * R + (b & (NS - 1));
+            for (int i = 0; i < NB; ++i) {
+                const int b = j + i * TPL;
+                const int base = (b / NS) * NS * R + (b & (NS - 1));
 #pragma unroll
-            for (int r = 0; r < R; ++r) line[lpad<N>(base + r * NS)] = v[i * R + r];
+                for (int r = 0; r < R; ++r) line[lpad<N>(base + r * NS)] = v[i * R + r];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < NB2; ++i) {
+                const int b = j + i * TPL;
+#pragma unroll
+                for (int r = 0; r < R2; ++r) v[i * R2 + r] = line[lpad<N>(b + r * (N / R2))];
+            }
+        } else {
+            // Real parts, then imaginary parts, through the same array.  The
+            // second write reads only .y, which the first read left alone.
+            Real *line = static_cast<Real *>(line_base);
+#pragma unroll
+            for (int part = 0; part < 2; ++part) {
+                if (STG > 0 || part > 0) __syncthreads();
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    const int b = j + i * TPL;
+                    const int base = (b / NS) * NS * R + (b & (NS - 1));
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        line[lpad<N>(base + r * NS)] = part ? v[i * R + r].y : v[i * R + r].x;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < NB2; ++i) {
+                    const int b = j + i * TPL;
+#pragma unroll
+                    for (int r = 0; r < R2; ++r) {
+                        const Real x = line[lpad<N>(b + r * (N / R2))];
+                        if (part) v[i * R2 + r].y = x;
+                        else v[i * R2 + r].x = x;
+                    }
+                }
+            }
         }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < NB2; ++i) {
-            const int b = j + i * TPL;
-#pragma unroll
-            for (int r = 0; r < R2; ++r) v[i * R2 + r] = line[lpad<N>(b + r * (N / R2))];
-        }
-        run_stages<C, N, RMAX, STG + 1>(v, line, twl, j);
+        run_stages<C, N, RMAX, E, SPLIT, STG + 1>(v, line_base, twl, j);
     }
 }
 

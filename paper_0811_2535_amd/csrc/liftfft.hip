@@ -48,42 +48,65 @@ struct PassArgs {
     const void *tw_lo; // pass 1: w_n^b, b < 2^log2h
     int64_t lines;     // batch * lines per transform
     int64_t n;         // transform length
+    int64_t ntiles;    // tiles of T lines
     int32_t log2p, log2q;
     int32_t log2T;  // lines per tile of this kernel
     int32_t log2T1; // lines per tile of pass 1 (scratch tile width)
     int32_t log2h;
     int32_t conj_in, conj_out;
     int32_t xcd_remap;
+    int32_t pitch;  // exchange line pitch, in exchange elements
 };
 
-// Workgroup -> tile.  Workgroups are dispatched round-robin over the 8 XCDs;
-// with the remap each XCD owns a contiguous range of tiles, so tiles that
-// share cache lines (adjacent columns in pass 1, adjacent rows in pass 2) are
-// in flight in the same L2 at the same time.
-__device__ __forceinline__ int64_t tile_index(int remap) {
-    const int64_t bid = blockIdx.x, G = gridDim.x;
-    if (remap) return (bid & 7) * (G >> 3) + (bid >> 3); // G is a multiple of 8
-    return bid;
+// Workgroup g's k-th tile, or -1.  Workgroups are dispatched round-robin over
+// the 8 XCDs; with the remap each XCD owns a contiguous range of tiles, so
+// tiles that share cache lines (adjacent columns in pass 1, adjacent rows in
+// pass 2) are in flight in the same L2 at the same time.  A persistent
+// workgroup walks its XCD's range with stride (workgroups per XCD).
+template <bool PERSIST> __device__ __forceinline__ int64_t tile_of(const PassArgs &a, int64_t k) {
+    const int64_t g = blockIdx.x, G = gridDim.x;
+    if constexpr (!PERSIST) {
+        if (k) return -1;
+        return a.xcd_remap ? (g & 7) * (G >> 3) + (g >> 3) : g; // G is a multiple of 8
+    } else {
+        if (a.xcd_remap) { // G and ntiles are multiples of 8
+            const int64_t per = a.ntiles >> 3, loc = k * (G >> 3) + (g >> 3);
+            return loc < per ? (g & 7) * per + loc : -1;
+        }
+        const int64_t t = k * G + g;
+        return t < a.ntiles ? t : -1;
+    }
 }
 
-// Largest workgroup: 1024 threads for complex64, 512 for complex128 (whose
-// tiles keep up to 256 VGPRs per lane).
-template <typename Real> constexpr int max_threads() { return sizeof(Real) == 4 ? 1024 : 512; }
+// Largest workgroup: 1024 threads for complex64 with 16 values per thread;
+// 512 (up to 256 VGPRs per lane) for complex128, for 32 values per thread
+// and for persistent kernels, which hold the next tile in registers too.
+template <typename Real, int EMAX, bool PERSIST> constexpr int max_threads() {
+    return sizeof(Real) == 4 && !PERSIST ? 1024 : 512;
+}
+// Minimum waves per SIMD the register allocation must allow: 8 (64 VGPRs,
+// two 1024-thread workgroups per CU) for the dense variants, else 1.
+template <bool DENSE> constexpr int min_waves() { return DENSE ? 8 : 1; }
 
-// One launch of a pass: each workgroup transforms one tile of T consecutive
-// lines.  All data accesses go through buffer descriptors covering exactly
-// the tile's range.
-template <typename Real, int N, int RMAX, int KIND>
-__global__ __launch_bounds__(max_threads<Real>()) void pass_kernel(PassArgs a) {
+// One launch of a pass.  Each workgroup transforms tiles of T consecutive
+// lines: one tile, or (PERSIST) a sequence of tiles with the loads of the
+// next tile issued before the current one is transformed.  All data accesses
+// go through buffer descriptors covering exactly the tile's range.
+//   EMAX   complex values per thread (16 or 32)
+//   SPLIT  exchange real and imaginary parts in turn (half the LDS)
+//   DENSE  registers capped at 64 VGPRs so that two 1024-thread
+//          workgroups share a CU
+template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, bool PERSIST, bool DENSE>
+__global__ __launch_bounds__((max_threads<Real, EMAX, PERSIST>()), (min_waves<DENSE>())) void pass_kernel(
+    PassArgs a) {
     using C = typename Cx<Real>::T;
+    using L = typename std::conditional<SPLIT, Real, C>::type; // exchange element
     constexpr uint32_t ES = sizeof(C);
-    constexpr int E = vals_per_thread(N), TPL = N / E;
+    constexpr int E = vals_per_thread(N, EMAX), TPL = N / E;
     constexpr int NST = sched_nstages(N, RMAX);
     constexpr int R0 = sched_radix(N, RMAX, 0), RL = sched_radix(N, RMAX, NST - 1);
-    constexpr int PITCH = line_pitch(N);
     constexpr bool TILE = uses_tile(N, RMAX);
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C *lds = reinterpret_cast<C *>(smem_raw);
 
     const int log2T = a.log2T, T = 1 << log2T;
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -95,35 +118,37 @@ __global__ __launch_bounds__(max_threads<Real>()) void pass_kernel(PassArgs a) {
         j = tid & (TPL - 1); // lanes sweep one contiguous line first
         c = tid / TPL;
     }
-    const int64_t line0 = tile_index(a.xcd_remap) << log2T; // workgroup-uniform
-    const bool active = line0 + c < a.lines;
-    C *twl = lds + (TILE ? T * PITCH : 0);
-    C *ep = twl + (TILE ? tw_total(N, RMAX) : 0);
+    L *line = reinterpret_cast<L *>(smem_raw) + c * a.pitch;
+    C *twl = reinterpret_cast<C *>(smem_raw + lds_tile_bytes(N, RMAX, T, a.pitch, sizeof(L)));
+    C *ep_base = reinterpret_cast<C *>(smem_raw + lds_ep_offset(N, RMAX, T, a.pitch, sizeof(L), sizeof(C)));
     const Real sin_ = a.conj_in ? Real(-1) : Real(1);
     const Real sout = a.conj_out ? Real(-1) : Real(1);
     const C *__restrict__ in = static_cast<const C *>(a.in);
     C *__restrict__ out = static_cast<C *>(a.out);
     const int64_t pmask = (int64_t(1) << a.log2p) - 1, qmask = (int64_t(1) << a.log2q) - 1;
 
-    // 1. Data loads: a buffer descriptor over the tile's range, one 32-bit
-    //    lane offset, and a uniform per-slot offset.
-    C v[E];
-    if (active) {
+    // Data loads of the tile starting at line0: a buffer descriptor over the
+    // tile's range, one 32-bit lane offset, and a uniform per-slot offset.
+    auto load = [&](int64_t line0, C *v) {
+        if (line0 + c >= a.lines) {
+#pragma unroll
+            for (int s = 0; s < E; ++s) v[s] = mk<C>(Real(0), Real(0));
+            return;
+        }
         if constexpr (KIND == K_SINGLE) {
             const int64_t nl = a.lines - line0 < T ? a.lines - line0 : T;
             const rsrc_t src = make_rsrc(in + line0 * N, uint32_t(nl * N) * ES);
             const uint32_t lane = (uint32_t(c) * N + uint32_t(j)) * ES;
 #pragma unroll
             for (int s = 0; s < E; ++s)
-                v[s] = scale_im(buf_load(in, src, lane, uint32_t(slot_off<N, R0>(s)) * ES), sin_);
+                v[s] = scale_im(buf_load(in, src, lane, uint32_t(slot_off<N, E, R0>(s)) * ES), sin_);
         } else if constexpr (KIND == K_PASS1) {
             const int64_t b = line0 >> a.log2p, j10 = line0 & pmask;
             const rsrc_t src = make_rsrc(in + b * a.n + j10, uint32_t(a.n - j10) * ES);
             const uint32_t lane = (uint32_t(c) + (uint32_t(j) << a.log2p)) * ES;
 #pragma unroll
             for (int s = 0; s < E; ++s)
-                v[s] = scale_im(buf_load(in, src, lane, (uint32_t(slot_off<N, R0>(s)) << a.log2p) * ES),
-                                sin_);
+                v[s] = scale_im(buf_load(in, src, lane, (uint32_t(slot_off<N, E, R0>(s)) << a.log2p) * ES), sin_);
         } else {
             // Scratch layout S[j1/T1][k2][j1%T1]; the plan keeps T1 | TPL, so
             // j1 = j + off(s) with off(s) a multiple of T1.
@@ -134,65 +159,87 @@ __global__ __launch_bounds__(max_threads<Real>()) void pass_kernel(PassArgs a) {
                                    (uint32_t(c) << l2T1)) * ES;
 #pragma unroll
             for (int s = 0; s < E; ++s)
-                v[s] = scale_im(buf_load(in, src, lane, (uint32_t(slot_off<N, R0>(s)) << a.log2q) * ES),
-                                sin_);
+                v[s] = scale_im(buf_load(in, src, lane, (uint32_t(slot_off<N, E, R0>(s)) << a.log2q) * ES), sin_);
         }
-    } else {
-#pragma unroll
-        for (int s = 0; s < E; ++s) v[s] = mk<C>(Real(0), Real(0));
-    }
+    };
 
-    // 2. Weight tables into LDS (published by the first barrier of the stage
-    //    loop, or the explicit one below when the schedule has one stage).
+    // Transform the tile held in v and store it.  `ep` is this tile's buffer
+    // of the pass-1 weight table.
+    auto transform_store = [&](int64_t line0, C *v, C *ep) {
+        const bool active = line0 + c < a.lines;
+        C A = mk<C>(Real(1), Real(0));
+        if constexpr (KIND == K_PASS1) {
+            // Inter-pass weight w_n^(-j1*k2) with k2 = j + off(s): w_n^(j1*j)
+            // (per thread) times P[c][s] = w_n^(j1*off(s)) (per line, in
+            // LDS), both from the two-level FP64-generated tables.  The
+            // table is published by the first barrier of the stage loop (or
+            // the explicit one below when the schedule has one stage).
+            const C *__restrict__ hi = static_cast<const C *>(a.tw_hi);
+            const C *__restrict__ lo = static_cast<const C *>(a.tw_lo);
+            const int lomask = (1 << a.log2h) - 1;
+            const int j10 = int(line0 & pmask);
+            const int xa = (j10 + c) * j;
+            A = cmul(hi[xa >> a.log2h], lo[xa & lomask]);
+            for (int i = tid; i < T * (E + 1); i += nthr) {
+                const int cc = i / (E + 1), s = i - cc * (E + 1);
+                if (s >= E) continue;
+                const int off = (s / RL) * TPL + (s % RL) * (N / RL);
+                const int x = (j10 + cc) * off;
+                ep[i] = cmul(hi[x >> a.log2h], lo[x & lomask]);
+            }
+            if constexpr (!TILE) __syncthreads();
+        }
+
+        run_stages<C, N, RMAX, E, SPLIT>(v, line, twl, j);
+
+        if (!active) return;
+        if constexpr (KIND == K_SINGLE) {
+            const int64_t nl = a.lines - line0 < T ? a.lines - line0 : T;
+            const rsrc_t dst = make_rsrc(out + line0 * N, uint32_t(nl * N) * ES);
+            const uint32_t lane = (uint32_t(c) * N + uint32_t(j)) * ES;
+#pragma unroll
+            for (int s = 0; s < E; ++s)
+                buf_store(scale_im(v[s], sout), dst, lane, uint32_t(slot_off<N, E, RL>(s)) * ES);
+        } else if constexpr (KIND == K_PASS1) {
+            // Tile j1/T of the scratch array S[j1/T][k2][j1%T].
+            const int64_t b = line0 >> a.log2p, j10 = line0 & pmask;
+            const rsrc_t dst = make_rsrc(out + b * a.n + (j10 << a.log2q), uint32_t(T << a.log2q) * ES);
+            const uint32_t lane = ((uint32_t(j) << log2T) + uint32_t(c)) * ES;
+            const C *P = ep + c * (E + 1);
+#pragma unroll
+            for (int s = 0; s < E; ++s)
+                buf_store(cmulc(v[s], cmul(A, P[s])), dst, lane, (uint32_t(slot_off<N, E, RL>(s)) << log2T) * ES);
+        } else {
+            const int64_t b = line0 >> a.log2q, k20 = line0 & qmask;
+            const rsrc_t dst = make_rsrc(out + b * a.n + k20, uint32_t(a.n - k20) * ES);
+            const uint32_t lane = (uint32_t(c) + (uint32_t(j) << a.log2q)) * ES;
+#pragma unroll
+            for (int s = 0; s < E; ++s)
+                buf_store(scale_im(v[s], sout), dst, lane, (uint32_t(slot_off<N, E, RL>(s)) << a.log2q) * ES);
+        }
+    };
+
+    int64_t t = tile_of<PERSIST>(a, 0);
+    if (t < 0) return; // workgroup-uniform
+    C v[E];
+    load(t << log2T, v);
+    // Stage weight tables into LDS (published by the first barrier of the
+    // stage loop).
     if constexpr (TILE) fill_twiddles<C, N, RMAX>(twl, static_cast<const C *>(a.tw), tid, nthr);
-    C A = mk<C>(Real(1), Real(0));
-    if constexpr (KIND == K_PASS1) {
-        // Inter-pass weight w_n^(-j1*k2) with k2 = j + off(s): w_n^(j1*j)
-        // (per thread) times P[c][s] = w_n^(j1*off(s)) (per line, in LDS),
-        // both from the two-level FP64-generated tables.
-        const C *__restrict__ hi = static_cast<const C *>(a.tw_hi);
-        const C *__restrict__ lo = static_cast<const C *>(a.tw_lo);
-        const int lomask = (1 << a.log2h) - 1;
-        const int j10 = int(line0 & pmask);
-        const int xa = (j10 + c) * j;
-        A = cmul(hi[xa >> a.log2h], lo[xa & lomask]);
-        for (int i = tid; i < T * (E + 1); i += nthr) {
-            const int cc = i / (E + 1), s = i - cc * (E + 1);
-            if (s >= E) continue;
-            const int off = (s / RL) * TPL + (s % RL) * (N / RL);
-            const int x = (j10 + cc) * off;
-            ep[i] = cmul(hi[x >> a.log2h], lo[x & lomask]);
-        }
-        if constexpr (!TILE) __syncthreads();
-    }
-
-    run_stages<C, N, RMAX>(v, lds + c * PITCH, twl, j);
-
-    // 3. Stores.
-    if (!active) return;
-    if constexpr (KIND == K_SINGLE) {
-        const int64_t nl = a.lines - line0 < T ? a.lines - line0 : T;
-        const rsrc_t dst = make_rsrc(out + line0 * N, uint32_t(nl * N) * ES);
-        const uint32_t lane = (uint32_t(c) * N + uint32_t(j)) * ES;
-#pragma unroll
-        for (int s = 0; s < E; ++s)
-            buf_store(scale_im(v[s], sout), dst, lane, uint32_t(slot_off<N, RL>(s)) * ES);
-    } else if constexpr (KIND == K_PASS1) {
-        // Tile j1/T of the scratch array S[j1/T][k2][j1%T].
-        const int64_t b = line0 >> a.log2p, j10 = line0 & pmask;
-        const rsrc_t dst = make_rsrc(out + b * a.n + (j10 << a.log2q), uint32_t(T << a.log2q) * ES);
-        const uint32_t lane = ((uint32_t(j) << log2T) + uint32_t(c)) * ES;
-        const C *P = ep + c * (E + 1);
-#pragma unroll
-        for (int s = 0; s < E; ++s)
-            buf_store(cmulc(v[s], cmul(A, P[s])), dst, lane, (uint32_t(slot_off<N, RL>(s)) << log2T) * ES);
+    if constexpr (!PERSIST) {
+        transform_store(t << log2T, v, ep_base);
     } else {
-        const int64_t b = line0 >> a.log2q, k20 = line0 & qmask;
-        const rsrc_t dst = make_rsrc(out + b * a.n + k20, uint32_t(a.n - k20) * ES);
-        const uint32_t lane = (uint32_t(c) + (uint32_t(j) << a.log2q)) * ES;
+        C w[E];
+        for (int64_t k = 0;; ++k) {
+            const int64_t tn = tile_of<PERSIST>(a, k + 1);
+            if (tn >= 0) load(tn << log2T, w); // in flight while this tile is transformed
+            if (k > 0) __syncthreads();        // the previous tile's LDS readers are done
+            transform_store(t << log2T, v, ep_base + (k & 1) * T * (E + 1));
+            if (tn < 0) break;
 #pragma unroll
-        for (int s = 0; s < E; ++s)
-            buf_store(scale_im(v[s], sout), dst, lane, (uint32_t(slot_off<N, RL>(s)) << a.log2q) * ES);
+            for (int s = 0; s < E; ++s) v[s] = w[s];
+            t = tn;
+        }
     }
 }
 
@@ -215,19 +262,36 @@ __global__ void twiddle_table_kernel(typename Cx<Real>::T *out, int64_t count, i
 
 using KernelFn = void (*)(PassArgs);
 
-template <typename Real, int KIND, int RMAX, int... L>
-constexpr std::array<KernelFn, sizeof...(L)> kernel_row(std::integer_sequence<int, L...>) {
-    return {{(L == 0 ? nullptr : &pass_kernel<Real, (1 << (L == 0 ? 1 : L)), RMAX, KIND>)...}};
+// Kernel variant of the pass kernels.
+struct Variant {
+    int emax = 16;        // complex values per thread
+    bool split = false;   // real/imaginary exchange in turn
+    bool persist = false; // persistent workgroups with next-tile prefetch
+    bool dense = false;   // 64-VGPR cap (two 1024-thread workgroups per CU)
+    bool is_default() const { return emax == 16 && !split && !persist && !dense; }
+    int code() const { return (emax == 32 ? 1 : 0) | (split ? 2 : 0) | (persist ? 4 : 0) | (dense ? 8 : 0); }
+};
+
+template <typename Real, int KIND, int RMAX, int VAR, int LMIN, int L> constexpr KernelFn kernel_entry() {
+    if constexpr (L < LMIN || L < 1) return nullptr;
+    else
+        return &pass_kernel<Real, (1 << L), RMAX, KIND, (VAR & 1) ? 32 : 16, (VAR & 2) != 0, (VAR & 4) != 0,
+                            (VAR & 8) != 0>;
 }
 
-template <typename Real, int KIND, int RMAX> KernelFn pick(int log2N) {
+template <typename Real, int KIND, int RMAX, int VAR, int LMIN, int... L>
+constexpr std::array<KernelFn, sizeof...(L)> kernel_row(std::integer_sequence<int, L...>) {
+    return {{kernel_entry<Real, KIND, RMAX, VAR, LMIN, L>()...}};
+}
+
+template <typename Real, int KIND, int RMAX, int VAR = 0, int LMIN = 1> KernelFn pick(int log2N) {
     static const auto row =
-        kernel_row<Real, KIND, RMAX>(std::make_integer_sequence<int, MAX_LOG2_LINE + 1>{});
+        kernel_row<Real, KIND, RMAX, VAR, LMIN>(std::make_integer_sequence<int, MAX_LOG2_LINE + 1>{});
     if (log2N < 1 || log2N > MAX_LOG2_LINE) return nullptr;
     return row[log2N];
 }
 
-template <typename Real> KernelFn pick_real(int kind, int log2N, int rmax) {
+template <typename Real> KernelFn pick_default(int kind, int log2N, int rmax) {
     switch (kind * 100 + rmax) {
     case K_SINGLE * 100 + 16: return pick<Real, K_SINGLE, 16>(log2N);
     case K_SINGLE * 100 + 2: return pick<Real, K_SINGLE, 2>(log2N);
@@ -239,9 +303,37 @@ template <typename Real> KernelFn pick_real(int kind, int log2N, int rmax) {
     }
 }
 
-KernelFn pick_kernel(int dtype, int kind, int log2N, int rmax) {
-    return dtype == FFT_C64 ? pick_real<float>(kind, log2N, rmax)
-                            : pick_real<double>(kind, log2N, rmax);
+// The other variants exist for complex64 pass kernels with radix 16 and lines
+// of 2^10..2^12 (the lifts of the largest transforms).
+constexpr int VARIANT_LMIN = 10;
+
+template <int KIND> KernelFn pick_variant(int log2N, const Variant &v) {
+    switch (v.code()) {
+    case 1: return pick<float, KIND, 16, 1, VARIANT_LMIN>(log2N);
+    case 2: return pick<float, KIND, 16, 2, VARIANT_LMIN>(log2N);
+    case 3: return pick<float, KIND, 16, 3, VARIANT_LMIN>(log2N);
+    case 4: return pick<float, KIND, 16, 4, VARIANT_LMIN>(log2N);
+    case 5: return pick<float, KIND, 16, 5, VARIANT_LMIN>(log2N);
+    case 6: return pick<float, KIND, 16, 6, VARIANT_LMIN>(log2N);
+    case 7: return pick<float, KIND, 16, 7, VARIANT_LMIN>(log2N);
+    case 8: return pick<float, KIND, 16, 8, VARIANT_LMIN>(log2N);
+    case 10: return pick<float, KIND, 16, 10, VARIANT_LMIN>(log2N);
+    default: return nullptr; // dense variants exist with 16 values per thread, one tile each
+    }
+}
+
+KernelFn pick_kernel(int dtype, int kind, int log2N, int rmax, const Variant &v) {
+    if (v.is_default())
+        return dtype == FFT_C64 ? pick_default<float>(kind, log2N, rmax)
+                                : pick_default<double>(kind, log2N, rmax);
+    if (dtype != FFT_C64 || rmax != 16) return nullptr;
+    if (kind == K_PASS1) return pick_variant<K_PASS1>(log2N, v);
+    if (kind == K_PASS2) return pick_variant<K_PASS2>(log2N, v);
+    return nullptr;
+}
+
+int thread_cap(size_t esize, const Variant &v) {
+    return esize == 8 && !v.persist ? max_threads<float, 16, false>() : 512;
 }
 
 int ilog2_exact(int64_t v) {
@@ -253,9 +345,11 @@ int ilog2_exact(int64_t v) {
 
 struct Launch {
     KernelFn fn = nullptr;
+    Variant var;
     int log2N = 0, log2T = 0;
     int64_t lines = 0, ntiles = 0, grid = 0;
     int threads = 0;
+    int pitch = 0;
     size_t lds = 0;
     bool remap = false;
 };
@@ -284,62 +378,105 @@ struct fft_plan {
 
 namespace {
 
+// Exchange pitch and LDS bytes of a tile of 2^log2T lines.
+struct TileShape {
+    int pitch = 0;
+    int64_t lds = 0;
+};
+TileShape tile_shape(int log2N, int rmax, size_t esize, int log2T, const Variant &v, int kind) {
+    const int N = 1 << log2N, E = vals_per_thread(N, v.emax), T = 1 << log2T;
+    const int lsize = int(v.split ? esize / 2 : esize);
+    TileShape ts;
+    ts.pitch = exchange_pitch(N, T, N / E, lsize, kind != K_SINGLE);
+    ts.lds = lds_bytes(N, rmax, T, E, ts.pitch, lsize, int(esize), kind == K_PASS1);
+    return ts;
+}
+
 // Lines per tile: the smallest power of two T <= max_lines whose tile has at
 // least `want_threads` threads and `min_T` lines, as long as it fits the
-// thread and LDS limits; `cap` (0 = none) bounds T.
-int choose_log2T(int log2N, int rmax, size_t esize, int64_t max_lines, int want_threads,
-                 int min_T, int cap, bool epilogue) {
-    const int64_t thread_cap = esize == 8 ? max_threads<float>() : max_threads<double>();
+// thread and LDS limits and `cap` (0 = none).
+int choose_log2T(int log2N, int rmax, size_t esize, int64_t max_lines, int want_threads, int min_T,
+                 int cap, int kind, const Variant &v) {
     const int N = 1 << log2N;
-    const int64_t tpl = N / vals_per_thread(N);
-    auto fits = [&](int64_t T) {
-        return T <= max_lines && T * tpl <= thread_cap &&
-               int64_t(lds_elems(N, rmax, int(T), epilogue)) * int64_t(esize) <= LDS_BUDGET &&
-               (!cap || T <= cap);
+    const int64_t tpl = N / vals_per_thread(N, v.emax);
+    const int64_t tcap = thread_cap(esize, v);
+    auto fits = [&](int l2T) {
+        const int64_t T = int64_t(1) << l2T;
+        return T <= max_lines && T * tpl <= tcap &&
+               tile_shape(log2N, rmax, esize, l2T, v, kind).lds <= LDS_BUDGET && (!cap || T <= cap);
     };
     int log2T = 0;
     for (;;) {
         const int64_t T = int64_t(1) << log2T;
         if (T * tpl >= want_threads && T >= min_T) break;
-        if (!fits(2 * T)) break;
+        if (!fits(log2T + 1)) break;
         ++log2T;
     }
     return log2T;
 }
 
-// Fill a launch description: tile shape, LDS and grid (one workgroup per
-// tile).
-bool fill_launch(Launch &L, int dtype, int kind, int log2N, int rmax, int log2T, int64_t lines) {
+// Fill a launch description: kernel, tile shape, LDS and grid (one
+// workgroup per tile, or for persistent kernels as many as are resident at
+// once).
+bool fill_launch(Launch &L, int dtype, int kind, int log2N, int rmax, int log2T, int64_t lines,
+                 const Variant &v, int device) {
     const int N = 1 << log2N;
     const size_t esize = dtype == FFT_C64 ? 8 : 16;
-    L.fn = pick_kernel(dtype, kind, log2N, rmax);
+    L.fn = pick_kernel(dtype, kind, log2N, rmax, v);
     if (!L.fn) return false;
+    L.var = v;
     L.log2N = log2N;
     L.log2T = log2T;
     L.lines = lines;
-    L.threads = (N / vals_per_thread(N)) << log2T;
+    L.threads = (N / vals_per_thread(N, v.emax)) << log2T;
+    if (L.threads > thread_cap(esize, v)) return false;
     L.ntiles = (lines + (int64_t(1) << log2T) - 1) >> log2T;
-    L.grid = L.ntiles;
-    L.lds = size_t(lds_elems(N, rmax, 1 << log2T, kind == K_PASS1)) * esize;
+    const TileShape ts = tile_shape(log2N, rmax, esize, log2T, v, kind);
+    if (ts.lds > LDS_BUDGET) return false;
+    L.pitch = ts.pitch;
+    L.lds = size_t(ts.lds);
     if (L.lds > 65536 &&
         hipFuncSetAttribute(reinterpret_cast<const void *>(L.fn),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(L.lds)) != hipSuccess) {
         (void)hipGetLastError();
         return false;
     }
-    L.remap = (L.grid % 8 == 0) && L.grid >= 16;
+    if (!v.persist) {
+        L.grid = L.ntiles;
+        L.remap = (L.grid % 8 == 0) && L.grid >= 16;
+    } else {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(L.fn),
+                                                         L.threads, L.lds) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        if (per_cu < 1) return false;
+        const int64_t resident = int64_t(per_cu) * cus;
+        L.grid = L.ntiles < resident ? L.ntiles : resident;
+        L.remap = L.ntiles % 8 == 0 && L.grid >= 16;
+        if (L.remap) L.grid &= ~int64_t(7);
+    }
     return L.grid <= INT32_MAX;
 }
 
-// Tile shape for a pass kernel: pass 1 aims at 512-thread tiles of at least
-// two lines (two workgroups per CU), pass 2 at tiles of at least four lines
-// (32-byte segments in the natural-order output), both capped by `cap`.
+// Tile shape for a pass kernel: `want_T` lines if nonzero (the launch then
+// fails if it does not fit), else pass 1 aims at 512-thread tiles of at least
+// two lines and pass 2 at tiles of at least four lines (32-byte segments in
+// the natural-order output), pass 1 within `cap1`.
 bool plan_pass(Launch &L, int dtype, int kind, int log2N, int rmax, int64_t lines_per_transform,
-               int64_t lines, int cap) {
+               int64_t lines, int want_T, int cap1, const Variant &v, int device) {
     const size_t esize = dtype == FFT_C64 ? 8 : 16;
-    const bool p1 = kind == K_PASS1;
-    const int l2T = choose_log2T(log2N, rmax, esize, lines_per_transform, 512, p1 ? 2 : 4, cap, p1);
-    return fill_launch(L, dtype, kind, log2N, rmax, l2T, lines);
+    int l2T;
+    if (want_T) {
+        l2T = ilog2_exact(want_T);
+        if (want_T > lines_per_transform || (cap1 && want_T > cap1)) return false;
+    } else {
+        const bool p1 = kind == K_PASS1;
+        l2T = choose_log2T(log2N, rmax, esize, lines_per_transform, 512, p1 ? 2 : 4, p1 ? cap1 : 0, kind, v);
+    }
+    return fill_launch(L, dtype, kind, log2N, rmax, l2T, lines, v, device);
 }
 
 int gen_table(int dtype, void *dst, int64_t count, int64_t mult, int log2N) {
@@ -447,7 +584,20 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
     if (o.log2_p < 0 || (o.log2_p && o.log2_p >= t)) return FFT_E_ARG;
     if (o.lines_per_block < 0 || (o.lines_per_block & (o.lines_per_block - 1))) return FFT_E_ARG;
     if (o.lines_per_block2 < 0 || (o.lines_per_block2 & (o.lines_per_block2 - 1))) return FFT_E_ARG;
-    if (o.flags & ~int32_t(FFT_OPT_NO_XCD_REMAP)) return FFT_E_ARG;
+    constexpr int32_t known_flags = FFT_OPT_NO_XCD_REMAP | FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE |
+                                    FFT_OPT_PERSISTENT | FFT_OPT_ONE_TILE | FFT_OPT_DENSE;
+    if (o.flags & ~known_flags) return FFT_E_ARG;
+    if ((o.flags & FFT_OPT_SPLIT_EXCHANGE) && (o.flags & FFT_OPT_FULL_EXCHANGE)) return FFT_E_ARG;
+    if ((o.flags & FFT_OPT_PERSISTENT) && (o.flags & FFT_OPT_ONE_TILE)) return FFT_E_ARG;
+    if (o.values_per_thread != 0 && o.values_per_thread != 16 && o.values_per_thread != 32)
+        return FFT_E_ARG;
+    // Pass-kernel variant: the defaults unless the options ask for another.
+    Variant var;
+    if (o.values_per_thread) var.emax = o.values_per_thread;
+    if (o.flags & FFT_OPT_SPLIT_EXCHANGE) var.split = true;
+    if (o.flags & FFT_OPT_PERSISTENT) var.persist = true;
+    if (o.flags & FFT_OPT_DENSE) var.dense = true;
+    const bool forced = !var.is_default();
 
     fft_plan *p = new (std::nothrow) fft_plan;
     if (!p) return FFT_E_OOM;
@@ -466,8 +616,13 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
     if (o.log2_p == 0 && t <= MAX_LOG2_LINE) {
         p->passes = 1;
         p->log2q = t;
-        const int l2T = choose_log2T(t, radix, esize, batch, 256, 1, o.lines_per_block, false);
-        if (!fill_launch(p->k1, dtype, K_SINGLE, t, radix, l2T, batch)) {
+        if (forced) { // the other variants are pass kernels only
+            free_plan(p);
+            return FFT_E_UNSUPPORTED;
+        }
+        const int l2T = o.lines_per_block ? ilog2_exact(o.lines_per_block)
+                                          : choose_log2T(t, radix, esize, batch, 256, 1, 0, K_SINGLE, var);
+        if (!fill_launch(p->k1, dtype, K_SINGLE, t, radix, l2T, batch, var, p->device)) {
             free_plan(p);
             return FFT_E_UNSUPPORTED;
         }
@@ -482,10 +637,22 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
         const int64_t P = int64_t(1) << p->log2p, Q = int64_t(1) << p->log2q;
         // Pass 2 reads the scratch tile layout of pass 1 with a separable
         // offset, which needs T1 | TPL2 (TPL2 = threads per pass-2 line).
-        const int tpl2 = int(P / vals_per_thread(int(P)));
-        const int cap1 = o.lines_per_block ? (o.lines_per_block < tpl2 ? o.lines_per_block : tpl2) : tpl2;
-        if (!plan_pass(p->k1, dtype, K_PASS1, p->log2q, radix, P, P * batch, cap1) ||
-            !plan_pass(p->k2, dtype, K_PASS2, p->log2p, radix, Q, Q * batch, o.lines_per_block2)) {
+        // Default variant per pass: complex64 radix-16 lines of 2^10..2^12 use
+        // the split exchange (measured faster at n = 2^24: the halved tile
+        // lets more tiles share a CU; see the design notes).
+        auto pass_variant = [&](int log2N) {
+            Variant v = var;
+            if (!forced && !(o.flags & FFT_OPT_FULL_EXCHANGE) && dtype == FFT_C64 && radix == 16 &&
+                log2N >= VARIANT_LMIN)
+                v.split = true;
+            return v;
+        };
+        const Variant var1 = pass_variant(p->log2q), var2 = pass_variant(p->log2p);
+        const int tpl2 = int(P / vals_per_thread(int(P), var2.emax));
+        if (!plan_pass(p->k1, dtype, K_PASS1, p->log2q, radix, P, P * batch, o.lines_per_block, tpl2, var1,
+                       p->device) ||
+            !plan_pass(p->k2, dtype, K_PASS2, p->log2p, radix, Q, Q * batch, o.lines_per_block2, 0, var2,
+                       p->device)) {
             free_plan(p);
             return FFT_E_UNSUPPORTED;
         }
@@ -585,6 +752,8 @@ int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void 
         a.out = out;
         a.tw = p->tw1;
         a.lines = p->k1.lines;
+        a.ntiles = p->k1.ntiles;
+        a.pitch = p->k1.pitch;
         a.log2T = a.log2T1 = p->k1.log2T;
         a.conj_in = a.conj_out = inv;
         a.xcd_remap = p->k1.remap;
@@ -597,6 +766,8 @@ int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void 
         a.tw_hi = p->tw_hi;
         a.tw_lo = p->tw_lo;
         a.lines = p->k1.lines;
+        a.ntiles = p->k1.ntiles;
+        a.pitch = p->k1.pitch;
         a.log2T = a.log2T1 = p->k1.log2T;
         a.conj_in = inv;
         a.conj_out = 0;
@@ -607,6 +778,8 @@ int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void 
         a.out = out;
         a.tw = p->tw2;
         a.lines = p->k2.lines;
+        a.ntiles = p->k2.ntiles;
+        a.pitch = p->k2.pitch;
         a.log2T = p->k2.log2T;
         a.log2T1 = p->k1.log2T;
         a.conj_in = 0;
@@ -648,6 +821,8 @@ int fft_plan_get_info(const fft_plan *p, fft_plan_info *info) {
     info->lds_bytes_pass2 = p->passes == 2 ? int64_t(p->k2.lds) : 0;
     info->scratch_bytes = int64_t(p->scratch_bytes);
     info->table_bytes = int64_t(p->table_bytes);
+    info->variant_pass1 = p->k1.var.code();
+    info->variant_pass2 = p->passes == 2 ? p->k2.var.code() : 0;
     return FFT_OK;
 }
 

@@ -43,7 +43,7 @@ def test_binding_lists_match_header():
 
 
 def test_abi_version():
-    assert _lib().fft_abi_version() == 100
+    assert _lib().fft_abi_version() == 101
 
 
 def test_strerror_covers_codes():
@@ -75,11 +75,19 @@ def test_create_rejects_bad_options():
     for opts, want in cases:
         assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(opts), ctypes.byref(h)) == want
     bad = PlanOpts(0, 0, 0, 0, 0)
-    bad.reserved[2] = 1
+    bad.reserved[1] = 1
     assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(PlanOpts(0, 0, 0, 3, 0)),
                                 ctypes.byref(h)) == -9
+    # contradictory flags: split and full exchange; persistent and one tile
     assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(PlanOpts(0, 0, 0, 0, 6)),
                                 ctypes.byref(h)) == -9
+    assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(PlanOpts(0, 0, 0, 0, 24)),
+                                ctypes.byref(h)) == -9
+    assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(PlanOpts(0, 0, 0, 0, 64)),
+                                ctypes.byref(h)) == -9
+    for vpt in (-16, 8, 64):
+        assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(PlanOpts(0, 0, 0, 0, 0, vpt)),
+                                    ctypes.byref(h)) == -9
     assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(bad), ctypes.byref(h)) == -9
     assert L.fft_plan_create(1024, 1, 0, None) == -4
 

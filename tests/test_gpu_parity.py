@@ -208,3 +208,74 @@ def test_timing_counts_launches(lf, torch):
     assert cnt == [1100, 1100] and ms[0] > 0 and ms[1] > 0
     plan.set_timing(False)
     plan.destroy()
+
+
+VARIANTS = [dict(values_per_thread=e, flags=f) for e in (16, 32) for f in (0, 2, 8, 10)] + \
+           [dict(values_per_thread=16, flags=f) for f in (32, 34)]
+
+
+def _variant_id(v):
+    names = {0: "full", 2: "split", 8: "full-persist", 10: "split-persist", 32: "full-dense",
+             34: "split-dense"}
+    return "e%d-%s" % (v["values_per_thread"], names[v["flags"]])
+
+
+@pytest.mark.parametrize("t,batch", [(20, 3), (23, 1), (24, 1)])
+def test_pass_kernel_variants(lf, t, batch):
+    """Every pass-kernel variant (16 or 32 values per thread; complex or
+    split real/imaginary exchange; one tile per workgroup or persistent
+    workgroups with next-tile prefetch) against the FP64 oracle, both signs,
+    at pass lines of 2^10, 2^11/2^12 and 2^12.  Variants with 16 values per
+    thread do the same operations in the same order as the default kernels
+    (up to which products the compiler fuses into FMAs), so their outputs
+    must also agree with the default plan to rounding level everywhere: a
+    stale or misplaced LDS value would show as an O(1) relative difference
+    in some element."""
+    x = datagen.signals(1 << t, batch, np.complex64, "normal", 300 + t)
+    for sign in (-1, 1):
+        ref = oracle.fft_batch(x.astype(np.complex128), sign)
+        announce("variants n=2^%d batch=%d sign=%d default" % (t, batch, sign))
+        base = run_plan(lf, x, sign)
+        for v in VARIANTS:
+            announce("variants n=2^%d batch=%d sign=%d %s" % (t, batch, sign, _variant_id(v)))
+            got = run_plan(lf, x, sign, **v)
+            errs = [oracle.rel_l2(got[b], ref[b]) for b in range(batch)]
+            assert max(errs) <= TOL[np.complex64], (_variant_id(v), errs)
+            if v["values_per_thread"] == 16:
+                assert_rounding_level(got, base, _variant_id(v))
+
+
+def assert_rounding_level(got, base, what):
+    """Element-wise agreement of two FP32 results to a few units in the last
+    place of the largest output (|X_k| is at most sum |x_j|)."""
+    scale = np.abs(base).max()
+    diff = np.abs(got.astype(np.complex128) - base.astype(np.complex128))
+    worst = float(diff.max() / scale)
+    assert worst <= 1e-5, (what, worst, np.unravel_index(int(np.argmax(diff)), diff.shape))
+
+
+def test_variant_tile_widths(lf):
+    """Persistent and split variants over the tile widths the planner may
+    pick (1..8 lines in pass 1, 2..8 in pass 2), against the oracle and,
+    with 16 values per thread, element-wise against the default plan."""
+    import torch
+    t, batch = 22, 2
+    x = datagen.signals(1 << t, batch, np.complex64, "normal", 322)
+    ref = oracle.fft_batch(x.astype(np.complex128), -1)
+    base = run_plan(lf, x, -1)
+    for v in VARIANTS:
+        for T1, T2 in ((1, 2), (2, 4), (4, 8), (8, 8)):
+            try:
+                plan = lf.Plan(1 << t, batch, torch.complex64, lines_per_block=T1, lines_per_block2=T2, **v)
+            except lf.FFTError:
+                continue
+            info = plan.info()
+            plan.destroy()
+            if info["lines_per_block_pass1"] != T1 or info["lines_per_block_pass2"] != T2:
+                continue
+            announce("variant tiles %s T=(%d,%d)" % (_variant_id(v), T1, T2))
+            got = run_plan(lf, x, -1, lines_per_block=T1, lines_per_block2=T2, **v)
+            errs = [oracle.rel_l2(got[b], ref[b]) for b in range(batch)]
+            assert max(errs) <= TOL[np.complex64], (_variant_id(v), T1, T2, errs)
+            if v["values_per_thread"] == 16:
+                assert_rounding_level(got, base, (_variant_id(v), T1, T2))
