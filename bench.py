@@ -138,6 +138,58 @@ def cpu_baseline(x0, x1, y0_gpu, y1_gpu):
     return base, parity
 
 
+def measure_fwd_bwd(torch, lf, datagen, reps: int = 5) -> dict:
+    """Differentiation form on batch 8 x n = 2^22 complex64 (N(0,1) inputs,
+    weights U[0,1], seed 5): loss = sum w |F x|^2 through the autograd
+    Function, whose backward is the adjoint (sign +1) transform.  Reports the
+    whole forward+backward step, the two transforms inside it (plan timing),
+    and the same two transforms run as plain executes."""
+    import numpy as np
+    n, batch = 1 << 22, 8
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(datagen.signals(n, batch, np.complex64, "normal", 5)).to(dev).requires_grad_()
+    w = torch.from_numpy(datagen.real_weights(n, batch, 5).astype(np.float32)).to(dev)
+    plan = lf.cached_plan(n, batch, torch.complex64, dev)
+
+    def step():
+        y = lf.LiftFFT.apply(x, -1)
+        loss = (w * (y.real * y.real + y.imag * y.imag)).sum()
+        loss.backward()
+        x.grad = None
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.read_timing(reset=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / reps
+    kms, kcnt = plan.read_timing(reset=True)
+    fft_ms_ad = (kms[0] + kms[1]) / reps  # two transforms per step
+    y = torch.empty_like(x.detach())
+    g = torch.empty_like(y)
+    xd = x.detach()
+    for _ in range(reps):
+        plan.execute(xd, y, -1)
+        plan.execute(y, g, 1)
+    kms, kcnt = plan.read_timing(reset=True)
+    plan.set_timing(False)
+    fft_ms_plain = (kms[0] + kms[1]) / reps
+    flops = 2 * 5.0 * n * math.log2(n) * batch
+    return {"workload": "c64 batch 8 x n=2^22, loss sum w|Fx|^2, forward + adjoint backward",
+            "ms_step_total": round(ms_step, 4),
+            "ms_two_ffts_in_autograd": round(fft_ms_ad, 4),
+            "ms_two_plain_executes": round(fft_ms_plain, 4),
+            "ratio_vs_plain": round(fft_ms_ad / fft_ms_plain, 4),
+            "gflops_ffts": round(flops / (fft_ms_ad * 1e-3) / 1e9, 1),
+            "hbm_gbps_ffts": round(2 * 32 * n * batch / (fft_ms_ad * 1e-3) / 1e9, 1)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +198,8 @@ def main() -> int:
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--sets", type=int, default=4, help="buffer sets rotated between transforms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the differentiation-form measurement")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary from two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of this benchmark and exit")
@@ -299,6 +353,11 @@ def main() -> int:
         },
         "wall_s": round(wall, 4),
     }
+    if not args.no_extras:
+        print("[bench] forward + adjoint backward, batch 8 x 2^22", file=sys.stderr, flush=True)
+        del xs, ys
+        result["fwd_bwd"] = measure_fwd_bwd(torch, lf, datagen)
+        lf.clear_plan_cache()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (FP64 oracle, 1 thread)", file=sys.stderr, flush=True)
         base, parity = cpu_baseline(host_inputs[0], host_inputs[1], y0, y1)

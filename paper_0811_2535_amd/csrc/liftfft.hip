@@ -24,6 +24,7 @@
 #include <string.h>
 
 #include <array>
+#include <type_traits>
 #include <new>
 #include <utility>
 #include <vector>
@@ -56,6 +57,8 @@ struct PassArgs {
     int32_t conj_in, conj_out;
     int32_t xcd_remap;
     int32_t pitch;  // exchange line pitch, in exchange elements
+    const int64_t *offsets; // packed uneven batch: first element of each transform (else b*n)
+    int64_t total;          // packed uneven batch: elements in the buffer
 };
 
 // Workgroup g's k-th tile, or -1.  Workgroups are dispatched round-robin over
@@ -88,122 +91,168 @@ template <typename Real, int EMAX, bool PERSIST> constexpr int max_threads() {
 // two 1024-thread workgroups per CU) for the dense variants, else 1.
 template <bool DENSE> constexpr int min_waves() { return DENSE ? 8 : 1; }
 
-// One launch of a pass.  Each workgroup transforms tiles of T consecutive
-// lines: one tile, or (PERSIST) a sequence of tiles with the loads of the
-// next tile issued before the current one is transformed.  All data accesses
-// go through buffer descriptors covering exactly the tile's range.
+// The work of one workgroup on tiles of T lines of one kernel shape:
+// loads, the pass-1 weights, the stage loop and the stores.  Shared by the
+// pass kernels below and the ragged-batch kernel.  All data accesses go
+// through buffer descriptors covering exactly the tile's range (for packed
+// batches of uneven lengths, `a.offsets` gives each transform's first
+// element and the single-pass descriptor covers the whole packed buffer).
 //   EMAX   complex values per thread (16 or 32)
 //   SPLIT  exchange real and imaginary parts in turn (half the LDS)
-//   DENSE  registers capped at 64 VGPRs so that two 1024-thread
-//          workgroups share a CU
-template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, bool PERSIST, bool DENSE>
-__global__ __launch_bounds__((max_threads<Real, EMAX, PERSIST>()), (min_waves<DENSE>())) void pass_kernel(
-    PassArgs a) {
+template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT> struct Tile {
     using C = typename Cx<Real>::T;
     using L = typename std::conditional<SPLIT, Real, C>::type; // exchange element
-    constexpr uint32_t ES = sizeof(C);
-    constexpr int E = vals_per_thread(N, EMAX), TPL = N / E;
-    constexpr int NST = sched_nstages(N, RMAX);
-    constexpr int R0 = sched_radix(N, RMAX, 0), RL = sched_radix(N, RMAX, NST - 1);
-    constexpr bool TILE = uses_tile(N, RMAX);
-    extern __shared__ __align__(16) unsigned char smem_raw[];
+    static constexpr uint32_t ES = sizeof(C);
+    static constexpr int E = vals_per_thread(N, EMAX), TPL = N / E;
+    static constexpr int NST = sched_nstages(N, RMAX);
+    static constexpr int R0 = sched_radix(N, RMAX, 0), RL = sched_radix(N, RMAX, NST - 1);
+    static constexpr bool TILE = uses_tile(N, RMAX);
 
-    const int log2T = a.log2T, T = 1 << log2T;
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    int c, j; // line within the tile, position within the line
-    if constexpr (KIND != K_SINGLE) {
-        c = tid & (T - 1); // lanes sweep the lines first: adjacent columns / rows
-        j = tid >> log2T;
-    } else {
-        j = tid & (TPL - 1); // lanes sweep one contiguous line first
-        c = tid / TPL;
+    const PassArgs &a;
+    int log2T, T, tid, nthr, c, j;
+    L *line;
+    C *twl, *ep_base;
+    Real sin_, sout;
+    const C *__restrict__ in;
+    C *__restrict__ out;
+    int64_t pmask, qmask;
+
+    __device__ __forceinline__ Tile(const PassArgs &args, unsigned char *smem) : a(args) {
+        log2T = a.log2T;
+        T = 1 << log2T;
+        tid = threadIdx.x;
+        nthr = blockDim.x;
+        if constexpr (KIND != K_SINGLE) {
+            c = tid & (T - 1); // lanes sweep the lines first: adjacent columns / rows
+            j = tid >> log2T;
+        } else {
+            j = tid & (TPL - 1); // lanes sweep one contiguous line first
+            c = tid / TPL;
+        }
+        line = reinterpret_cast<L *>(smem) + c * a.pitch;
+        twl = reinterpret_cast<C *>(smem + lds_tile_bytes(N, RMAX, T, a.pitch, sizeof(L)));
+        ep_base = reinterpret_cast<C *>(smem + lds_ep_offset(N, RMAX, T, a.pitch, sizeof(L), sizeof(C)));
+        sin_ = a.conj_in ? Real(-1) : Real(1);
+        sout = a.conj_out ? Real(-1) : Real(1);
+        in = static_cast<const C *>(a.in);
+        out = static_cast<C *>(a.out);
+        pmask = (int64_t(1) << a.log2p) - 1;
+        qmask = (int64_t(1) << a.log2q) - 1;
     }
-    L *line = reinterpret_cast<L *>(smem_raw) + c * a.pitch;
-    C *twl = reinterpret_cast<C *>(smem_raw + lds_tile_bytes(N, RMAX, T, a.pitch, sizeof(L)));
-    C *ep_base = reinterpret_cast<C *>(smem_raw + lds_ep_offset(N, RMAX, T, a.pitch, sizeof(L), sizeof(C)));
-    const Real sin_ = a.conj_in ? Real(-1) : Real(1);
-    const Real sout = a.conj_out ? Real(-1) : Real(1);
-    const C *__restrict__ in = static_cast<const C *>(a.in);
-    C *__restrict__ out = static_cast<C *>(a.out);
-    const int64_t pmask = (int64_t(1) << a.log2p) - 1, qmask = (int64_t(1) << a.log2q) - 1;
 
-    // Data loads of the tile starting at line0: a buffer descriptor over the
-    // tile's range, one 32-bit lane offset, and a uniform per-slot offset.
-    auto load = [&](int64_t line0, C *v) {
+    // First element of transform b.
+    __device__ __forceinline__ int64_t base(int64_t b) const { return a.offsets ? a.offsets[b] : b * a.n; }
+
+    // Single pass: descriptor and lane offset of this thread's line (the
+    // tile's contiguous range, or the whole packed buffer).
+    __device__ __forceinline__ void single_addr(int64_t line0, const C *buf, rsrc_t &r, uint32_t &lane) const {
+        if (a.offsets) {
+            r = make_rsrc(buf, uint32_t(a.total) * ES);
+            lane = (uint32_t(a.offsets[line0 + c]) + uint32_t(j)) * ES;
+        } else {
+            const int64_t nl = a.lines - line0 < T ? a.lines - line0 : T;
+            r = make_rsrc(buf + line0 * N, uint32_t(nl * N) * ES);
+            lane = (uint32_t(c) * N + uint32_t(j)) * ES;
+        }
+    }
+
+    // Data loads of the tile starting at line0: a buffer descriptor, one
+    // 32-bit lane offset, and a uniform per-slot offset.  Raw values: the
+    // conjugation of sign +1 is applied by the caller, so that a prefetch is
+    // not consumed (waited for) as soon as it is issued.
+    __device__ __forceinline__ void load(int64_t line0, C *v) const {
         if (line0 + c >= a.lines) {
 #pragma unroll
             for (int s = 0; s < E; ++s) v[s] = mk<C>(Real(0), Real(0));
             return;
         }
         if constexpr (KIND == K_SINGLE) {
-            const int64_t nl = a.lines - line0 < T ? a.lines - line0 : T;
-            const rsrc_t src = make_rsrc(in + line0 * N, uint32_t(nl * N) * ES);
-            const uint32_t lane = (uint32_t(c) * N + uint32_t(j)) * ES;
+            rsrc_t src;
+            uint32_t lane;
+            single_addr(line0, in, src, lane);
 #pragma unroll
-            for (int s = 0; s < E; ++s)
-                v[s] = scale_im(buf_load(in, src, lane, uint32_t(slot_off<N, E, R0>(s)) * ES), sin_);
+            for (int s = 0; s < E; ++s) v[s] = buf_load(in, src, lane, uint32_t(slot_off<N, E, R0>(s)) * ES);
         } else if constexpr (KIND == K_PASS1) {
             const int64_t b = line0 >> a.log2p, j10 = line0 & pmask;
-            const rsrc_t src = make_rsrc(in + b * a.n + j10, uint32_t(a.n - j10) * ES);
+            const rsrc_t src = make_rsrc(in + base(b) + j10, uint32_t(a.n - j10) * ES);
             const uint32_t lane = (uint32_t(c) + (uint32_t(j) << a.log2p)) * ES;
 #pragma unroll
             for (int s = 0; s < E; ++s)
-                v[s] = scale_im(buf_load(in, src, lane, (uint32_t(slot_off<N, E, R0>(s)) << a.log2p) * ES), sin_);
+                v[s] = buf_load(in, src, lane, (uint32_t(slot_off<N, E, R0>(s)) << a.log2p) * ES);
         } else {
             // Scratch layout S[j1/T1][k2][j1%T1]; the plan keeps T1 | TPL, so
             // j1 = j + off(s) with off(s) a multiple of T1.
             const int64_t b = line0 >> a.log2q, k20 = line0 & qmask;
             const int l2T1 = a.log2T1, T1 = 1 << l2T1;
-            const rsrc_t src = make_rsrc(in + b * a.n + (k20 << l2T1), uint32_t(a.n - (k20 << l2T1)) * ES);
-            const uint32_t lane = ((uint32_t(j >> l2T1) << (a.log2q + l2T1)) + uint32_t(j & (T1 - 1)) +
-                                   (uint32_t(c) << l2T1)) * ES;
+            const rsrc_t src = make_rsrc(in + base(b) + (k20 << l2T1), uint32_t(a.n - (k20 << l2T1)) * ES);
+            const uint32_t lane =
+                ((uint32_t(j >> l2T1) << (a.log2q + l2T1)) + uint32_t(j & (T1 - 1)) + (uint32_t(c) << l2T1)) * ES;
 #pragma unroll
             for (int s = 0; s < E; ++s)
-                v[s] = scale_im(buf_load(in, src, lane, (uint32_t(slot_off<N, E, R0>(s)) << a.log2q) * ES), sin_);
+                v[s] = buf_load(in, src, lane, (uint32_t(slot_off<N, E, R0>(s)) << a.log2q) * ES);
         }
-    };
+    }
 
-    // Transform the tile held in v and store it.  `ep` is this tile's buffer
-    // of the pass-1 weight table.
-    auto transform_store = [&](int64_t line0, C *v, C *ep) {
-        const bool active = line0 + c < a.lines;
-        C A = mk<C>(Real(1), Real(0));
-        if constexpr (KIND == K_PASS1) {
-            // Inter-pass weight w_n^(-j1*k2) with k2 = j + off(s): w_n^(j1*j)
-            // (per thread) times P[c][s] = w_n^(j1*off(s)) (per line, in
-            // LDS), both from the two-level FP64-generated tables.  The
-            // table is published by the first barrier of the stage loop (or
-            // the explicit one below when the schedule has one stage).
+    __device__ __forceinline__ void conj_in(C *v) const {
+#pragma unroll
+        for (int s = 0; s < E; ++s) v[s] = scale_im(v[s], sin_);
+    }
+
+    // Stage weight tables into LDS (published by the first barrier of the
+    // stage loop).
+    __device__ __forceinline__ void fill_tw() const {
+        if constexpr (TILE) fill_twiddles<C, N, RMAX>(twl, static_cast<const C *>(a.tw), tid, nthr);
+    }
+
+    // Pass 1: this tile's inter-pass weights.  w_n^(-j1*k2) with k2 = j +
+    // off(s) is w_n^(j1*j) (per thread, returned) times P[c][s] =
+    // w_n^(j1*off(s)) (per line, written to the LDS buffer `ep`), both from
+    // the two-level FP64-generated tables.  The LDS table is published by the
+    // first barrier of the stage loop (or the explicit one in transform_store
+    // when the schedule has one stage).
+    __device__ __forceinline__ int weight_exponent(int j10, int cc, int s) const {
+        return (j10 + cc) * ((s / RL) * TPL + (s % RL) * (N / RL));
+    }
+    __device__ __forceinline__ C weights(int64_t line0, C *ep) const {
+        if constexpr (KIND != K_PASS1) {
+            return mk<C>(Real(1), Real(0));
+        } else {
             const C *__restrict__ hi = static_cast<const C *>(a.tw_hi);
             const C *__restrict__ lo = static_cast<const C *>(a.tw_lo);
             const int lomask = (1 << a.log2h) - 1;
             const int j10 = int(line0 & pmask);
             const int xa = (j10 + c) * j;
-            A = cmul(hi[xa >> a.log2h], lo[xa & lomask]);
+            const C A = cmul(hi[xa >> a.log2h], lo[xa & lomask]);
             for (int i = tid; i < T * (E + 1); i += nthr) {
                 const int cc = i / (E + 1), s = i - cc * (E + 1);
                 if (s >= E) continue;
-                const int off = (s / RL) * TPL + (s % RL) * (N / RL);
-                const int x = (j10 + cc) * off;
+                const int x = weight_exponent(j10, cc, s);
                 ep[i] = cmul(hi[x >> a.log2h], lo[x & lomask]);
             }
-            if constexpr (!TILE) __syncthreads();
+            return A;
         }
+    }
+
+    // Transform the tile held in v and store it; `ep` and `A` are this
+    // tile's pass-1 weights.
+    __device__ __forceinline__ void transform_store(int64_t line0, C *v, const C *ep, C A) const {
+        const bool active = line0 + c < a.lines;
+        if constexpr (KIND == K_PASS1 && !TILE) __syncthreads();
 
         run_stages<C, N, RMAX, E, SPLIT>(v, line, twl, j);
 
         if (!active) return;
         if constexpr (KIND == K_SINGLE) {
-            const int64_t nl = a.lines - line0 < T ? a.lines - line0 : T;
-            const rsrc_t dst = make_rsrc(out + line0 * N, uint32_t(nl * N) * ES);
-            const uint32_t lane = (uint32_t(c) * N + uint32_t(j)) * ES;
+            rsrc_t dst;
+            uint32_t lane;
+            single_addr(line0, out, dst, lane);
 #pragma unroll
             for (int s = 0; s < E; ++s)
                 buf_store(scale_im(v[s], sout), dst, lane, uint32_t(slot_off<N, E, RL>(s)) * ES);
         } else if constexpr (KIND == K_PASS1) {
             // Tile j1/T of the scratch array S[j1/T][k2][j1%T].
             const int64_t b = line0 >> a.log2p, j10 = line0 & pmask;
-            const rsrc_t dst = make_rsrc(out + b * a.n + (j10 << a.log2q), uint32_t(T << a.log2q) * ES);
+            const rsrc_t dst = make_rsrc(out + base(b) + (j10 << a.log2q), uint32_t(T << a.log2q) * ES);
             const uint32_t lane = ((uint32_t(j) << log2T) + uint32_t(c)) * ES;
             const C *P = ep + c * (E + 1);
 #pragma unroll
@@ -211,33 +260,117 @@ __global__ __launch_bounds__((max_threads<Real, EMAX, PERSIST>()), (min_waves<DE
                 buf_store(cmulc(v[s], cmul(A, P[s])), dst, lane, (uint32_t(slot_off<N, E, RL>(s)) << log2T) * ES);
         } else {
             const int64_t b = line0 >> a.log2q, k20 = line0 & qmask;
-            const rsrc_t dst = make_rsrc(out + b * a.n + k20, uint32_t(a.n - k20) * ES);
+            const rsrc_t dst = make_rsrc(out + base(b) + k20, uint32_t(a.n - k20) * ES);
             const uint32_t lane = (uint32_t(c) + (uint32_t(j) << a.log2q)) * ES;
 #pragma unroll
             for (int s = 0; s < E; ++s)
                 buf_store(scale_im(v[s], sout), dst, lane, (uint32_t(slot_off<N, E, RL>(s)) << a.log2q) * ES);
         }
-    };
+    }
+
+    // One tile, start to finish (the caller orders it after any earlier
+    // readers of the LDS).
+    __device__ __forceinline__ void run_one(int64_t t) const {
+        C v[E];
+        load(t << log2T, v);
+        conj_in(v);
+        fill_tw();
+        const C A = weights(t << log2T, ep_base);
+        transform_store(t << log2T, v, ep_base, A);
+    }
+};
+
+// One launch of a pass.  Each workgroup transforms one tile, or (PERSIST) a
+// sequence of tiles with the loads of the next tile issued before the current
+// one is transformed.
+//   DENSE  registers capped at 64 VGPRs so that two 1024-thread
+//          workgroups share a CU
+template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, bool PERSIST, bool DENSE>
+__global__ __launch_bounds__((max_threads<Real, EMAX, PERSIST>()), (min_waves<DENSE>())) void pass_kernel(
+    PassArgs a) {
+    using W = Tile<Real, N, RMAX, KIND, EMAX, SPLIT>;
+    using C = typename W::C;
+    constexpr int E = W::E, TPL = W::TPL, RL = W::RL;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const W w(a, smem_raw);
 
     int64_t t = tile_of<PERSIST>(a, 0);
     if (t < 0) return; // workgroup-uniform
-    C v[E];
-    load(t << log2T, v);
-    // Stage weight tables into LDS (published by the first barrier of the
-    // stage loop).
-    if constexpr (TILE) fill_twiddles<C, N, RMAX>(twl, static_cast<const C *>(a.tw), tid, nthr);
     if constexpr (!PERSIST) {
-        transform_store(t << log2T, v, ep_base);
+        w.run_one(t);
     } else {
-        C w[E];
+        const int log2T = w.log2T, T = w.T, tid = w.tid, nthr = w.nthr;
+        C v[E];
+        w.load(t << log2T, v);
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            v[s] = scale_im(v[s], w.sin_);
+            // Materialise the first tile here: without this the conjugation
+            // is merged into the loop below, and the wait for the first
+            // tile's loads then also waits for every later prefetch.
+            __asm__ volatile("" : "+v"(v[s].x), "+v"(v[s].y));
+        }
+        w.fill_tw();
+        // The next tile's data and pass-1 weight inputs are loaded before this
+        // tile is transformed and consumed only after its stores are issued:
+        // loads complete in order, so any earlier use would also wait for them.
+        // Each thread fetches at most EPT entries of the weight table.
+        constexpr int EPT = 2;
+        static_assert(KIND != K_PASS1 || E * (E + 1) <= EPT * N, "weight entries per thread");
+        struct WeightLoads {
+            C ahi, alo, ehi[EPT], elo[EPT];
+        } wl;
+        auto fetch_weights = [&](int64_t line0) {
+            if constexpr (KIND == K_PASS1) {
+                const C *__restrict__ hi = static_cast<const C *>(a.tw_hi);
+                const C *__restrict__ lo = static_cast<const C *>(a.tw_lo);
+                const int lomask = (1 << a.log2h) - 1;
+                const int j10 = int(line0 & w.pmask);
+                const int xa = (j10 + w.c) * w.j;
+                wl.ahi = hi[xa >> a.log2h];
+                wl.alo = lo[xa & lomask];
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    const int i = tid + e * nthr, cc = i / (E + 1), s = i - cc * (E + 1);
+                    if (i < T * (E + 1) && s < E) {
+                        const int x = w.weight_exponent(j10, cc, s);
+                        wl.ehi[e] = hi[x >> a.log2h];
+                        wl.elo[e] = lo[x & lomask];
+                    }
+                }
+            }
+        };
+        auto publish_weights = [&](C *ep) -> C {
+            if constexpr (KIND != K_PASS1) {
+                return mk<C>(Real(1), Real(0));
+            } else {
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    const int i = tid + e * nthr, s = i % (E + 1);
+                    if (i < T * (E + 1) && s < E) ep[i] = cmul(wl.ehi[e], wl.elo[e]);
+                }
+                return cmul(wl.ahi, wl.alo);
+            }
+        };
+        (void)TPL;
+        (void)RL;
+        C nxt[E];
+        fetch_weights(t << log2T);
+        C A = publish_weights(w.ep_base);
         for (int64_t k = 0;; ++k) {
             const int64_t tn = tile_of<PERSIST>(a, k + 1);
-            if (tn >= 0) load(tn << log2T, w); // in flight while this tile is transformed
-            if (k > 0) __syncthreads();        // the previous tile's LDS readers are done
-            transform_store(t << log2T, v, ep_base + (k & 1) * T * (E + 1));
+            if (tn >= 0) { // in flight while this tile is transformed
+                fetch_weights(tn << log2T);
+                w.load(tn << log2T, nxt);
+            }
+            if (k > 0) __syncthreads(); // the previous tile's LDS readers are done
+            w.transform_store(t << log2T, v, w.ep_base + (k & 1) * T * (E + 1), A);
             if (tn < 0) break;
 #pragma unroll
-            for (int s = 0; s < E; ++s) v[s] = w[s];
+            for (int s = 0; s < E; ++s) v[s] = scale_im(nxt[s], w.sin_);
+            // Buffer (k+1)&1 was last read by the stores of tile k-1, which
+            // precede this tile's barriers.
+            A = publish_weights(w.ep_base + ((k + 1) & 1) * T * (E + 1));
             t = tn;
         }
     }
