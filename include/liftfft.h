@@ -131,8 +131,31 @@ typedef struct fft_plan_opts {
 } fft_plan_opts;
 
 /* As fft_plan_create with explicit options (opts may be NULL). */
+
 int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts *opts,
                        fft_plan **plan_out);
+
+/*
+ * A plan for `count` transforms of uneven power-of-two lengths in one packed
+ * buffer: transform i (length lengths[i] = 2^t_i, 1 <= t_i <= the dtype's
+ * maximum) occupies elements [off_i, off_i + lengths[i]) with off_i the sum
+ * of the earlier lengths.  The lengths are the run-time blocking parameters
+ * of one batch: the plan groups equal lengths into classes and covers them
+ * with two persistent launches (lengths up to 2^12 in one pass plus pass 1 of
+ * the longer ones, then pass 2 of the longer ones; Sections 4.2-4.8 of the
+ * paper for the lift), each walking a work list of tiles ordered by class,
+ * longest lines first.  fft_execute replays the two launches as one captured
+ * graph per (in, out, sign) triple (up to 16 per plan; then, or when the
+ * execute stream is itself being captured, the kernels are launched
+ * directly).  opts may be NULL; only flags = FFT_OPT_NO_GRAPH (launch
+ * directly) is accepted, anything else returns FFT_E_ARG.
+ * Errors: FFT_E_NULL (lengths or plan_out NULL), FFT_E_SIZE (count < 1, a
+ * length not a power of two >= 2), FFT_E_UNSUPPORTED (a length above the
+ * maximum, or a packed buffer of 2^32 bytes or more).
+ */
+enum { FFT_OPT_NO_GRAPH = 64 };
+int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const fft_plan_opts *opts,
+                         fft_plan **plan_out);
 
 /*
  * Execute the planned transforms: out = F_sign(in), as defined above.
@@ -167,7 +190,13 @@ const char *fft_strerror(int code);
  *   variant_pass1/2            kernel variant bits: 1 = 32 values per
  *                              thread, 2 = split exchange, 4 = persistent,
  *                              8 = dense (64-VGPR cap)
- * Pass-2 fields are 0 for single-pass plans.
+ *   length_classes, graph_launch  plans of uneven lengths: number of
+ *                              distinct lengths, and whether executes replay
+ *                              captured graphs (0 for single-length plans)
+ * Pass-2 fields are 0 for single-pass plans.  For plans of uneven lengths,
+ * n is the total element count, batch the number of transforms, and the
+ * pass-1/pass-2 fields describe the two persistent launches (single-pass
+ * lengths and pass 1 of the lifted ones; pass 2 of the lifted ones).
  */
 typedef struct fft_plan_info {
     int64_t n, batch;
@@ -178,6 +207,7 @@ typedef struct fft_plan_info {
     int64_t lds_bytes_pass1, lds_bytes_pass2;
     int64_t scratch_bytes, table_bytes;
     int32_t variant_pass1, variant_pass2;
+    int32_t length_classes, graph_launch;
 } fft_plan_info;
 
 int fft_plan_get_info(const fft_plan *plan, fft_plan_info *info);
@@ -194,7 +224,7 @@ int fft_plan_read_timing(fft_plan *plan, double ms_out[2], int64_t launches_out[
                          int reset);
 
 /* ABI version of this header (major*100 + minor). */
-#define LIFTFFT_ABI_VERSION 101
+#define LIFTFFT_ABI_VERSION 102
 int fft_abi_version(void);
 
 #ifdef __cplusplus

@@ -28,7 +28,7 @@ STATUS = {
 EXPORTED = [
     "fft_plan_create", "fft_plan_create_ex", "fft_execute", "fft_plan_destroy",
     "fft_strerror", "fft_plan_get_info", "fft_plan_set_timing", "fft_plan_read_timing",
-    "fft_abi_version",
+    "fft_abi_version", "fft_plan_create_many",
 ]
 
 
@@ -49,6 +49,7 @@ FFT_OPT_FULL_EXCHANGE = 4
 FFT_OPT_PERSISTENT = 8
 FFT_OPT_ONE_TILE = 16
 FFT_OPT_DENSE = 32
+FFT_OPT_NO_GRAPH = 64
 
 
 class PlanOpts(ctypes.Structure):
@@ -68,7 +69,8 @@ class PlanInfo(ctypes.Structure):
                 ("threads_pass1", ctypes.c_int32), ("threads_pass2", ctypes.c_int32),
                 ("lds_bytes_pass1", ctypes.c_int64), ("lds_bytes_pass2", ctypes.c_int64),
                 ("scratch_bytes", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
-                ("variant_pass1", ctypes.c_int32), ("variant_pass2", ctypes.c_int32)]
+                ("variant_pass1", ctypes.c_int32), ("variant_pass2", ctypes.c_int32),
+                ("length_classes", ctypes.c_int32), ("graph_launch", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -94,6 +96,8 @@ def lib():
             L.fft_plan_create.argtypes = [i64, i64, i32, ctypes.POINTER(vp)]
             L.fft_plan_create_ex.argtypes = [i64, i64, i32, ctypes.POINTER(PlanOpts),
                                              ctypes.POINTER(vp)]
+            L.fft_plan_create_many.argtypes = [ctypes.POINTER(i64), i64, i32, ctypes.POINTER(PlanOpts),
+                                               ctypes.POINTER(vp)]
             L.fft_execute.argtypes = [vp, vp, vp, i32, vp]
             L.fft_plan_destroy.argtypes = [vp]
             L.fft_strerror.argtypes = [i32]
@@ -102,7 +106,7 @@ def lib():
             L.fft_plan_set_timing.argtypes = [vp, i32]
             L.fft_plan_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double * 2),
                                                ctypes.POINTER(ctypes.c_int64 * 2), i32]
-            for name in ("fft_plan_create", "fft_plan_create_ex", "fft_execute",
+            for name in ("fft_plan_create", "fft_plan_create_ex", "fft_plan_create_many", "fft_execute",
                          "fft_plan_destroy", "fft_plan_get_info", "fft_plan_set_timing",
                          "fft_plan_read_timing", "fft_abi_version"):
                 getattr(L, name).restype = i32
@@ -134,6 +138,30 @@ class Plan:
     """A plan for ``batch`` transforms of length ``n`` (owns device memory).
 
     Thin wrapper over fft_plan_create_ex / fft_execute / fft_plan_destroy."""
+
+    @classmethod
+    def uneven(cls, lengths, dtype=torch.complex64, graph: bool = True) -> "Plan":
+        """A plan for transforms of the given power-of-two lengths packed back
+        to back in one buffer (fft_plan_create_many); ``self.offsets`` holds
+        each transform's first element."""
+        self = cls.__new__(cls)
+        self._h = ctypes.c_void_p()
+        lens = [int(v) for v in lengths]
+        arr = (ctypes.c_int64 * max(1, len(lens)))(*lens)
+        self.dtype_code = dtype_code(dtype)
+        self.torch_dtype = torch.complex64 if self.dtype_code == FFT_C64 else torch.complex128
+        opts = PlanOpts(0, 0, 0, 0, 0 if graph else FFT_OPT_NO_GRAPH)
+        rc = lib().fft_plan_create_many(arr, len(lens), self.dtype_code, ctypes.byref(opts),
+                                        ctypes.byref(self._h))
+        _check(rc, "fft_plan_create_many(count=%d)" % len(lens))
+        self.lengths = lens
+        self.offsets = [0] * len(lens)
+        acc = 0
+        for i, v in enumerate(lens):
+            self.offsets[i] = acc
+            acc += v
+        self.n, self.batch = acc, 1  # execute() checks the packed element count
+        return self
 
     def __init__(self, n: int, batch: int = 1, dtype=torch.complex64, log2_p: int = 0,
                  radix: int = 0, lines_per_block: int = 0, lines_per_block2: int = 0,

@@ -52,7 +52,7 @@ struct PassArgs {
     int64_t ntiles;    // tiles of T lines
     int32_t log2p, log2q;
     int32_t log2T;  // lines per tile of this kernel
-    int32_t log2T1; // lines per tile of pass 1 (scratch tile width)
+    int32_t log2T1; // scratch tile width W (lines of pass 1 per slab; divides pass 1's T)
     int32_t log2h;
     int32_t conj_in, conj_out;
     int32_t xcd_remap;
@@ -250,14 +250,18 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT> struct
             for (int s = 0; s < E; ++s)
                 buf_store(scale_im(v[s], sout), dst, lane, uint32_t(slot_off<N, E, RL>(s)) * ES);
         } else if constexpr (KIND == K_PASS1) {
-            // Tile j1/T of the scratch array S[j1/T][k2][j1%T].
+            // The tile's slabs of the scratch array S[j1/W][k2][j1%W]; the
+            // scratch width W = 2^log2T1 divides T (W = T in single-length
+            // plans).
             const int64_t b = line0 >> a.log2p, j10 = line0 & pmask;
+            const int lW = a.log2T1;
             const rsrc_t dst = make_rsrc(out + base(b) + (j10 << a.log2q), uint32_t(T << a.log2q) * ES);
-            const uint32_t lane = ((uint32_t(j) << log2T) + uint32_t(c)) * ES;
+            const uint32_t lane = ((uint32_t(c >> lW) << (a.log2q + lW)) + (uint32_t(j) << lW) +
+                                   uint32_t(c & ((1 << lW) - 1))) * ES;
             const C *P = ep + c * (E + 1);
 #pragma unroll
             for (int s = 0; s < E; ++s)
-                buf_store(cmulc(v[s], cmul(A, P[s])), dst, lane, (uint32_t(slot_off<N, E, RL>(s)) << log2T) * ES);
+                buf_store(cmulc(v[s], cmul(A, P[s])), dst, lane, (uint32_t(slot_off<N, E, RL>(s)) << lW) * ES);
         } else {
             const int64_t b = line0 >> a.log2q, k20 = line0 & qmask;
             const rsrc_t dst = make_rsrc(out + base(b) + k20, uint32_t(a.n - k20) * ES);
@@ -373,6 +377,85 @@ __global__ __launch_bounds__((max_threads<Real, EMAX, PERSIST>()), (min_waves<DE
             A = publish_weights(w.ep_base + ((k + 1) & 1) * T * (E + 1));
             t = tn;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Packed batches of uneven power-of-two lengths.  The plan groups the
+// transforms into classes of equal length; a class describes one kernel shape
+// (single pass, or pass 1 / pass 2 of the lift) over its transforms, whose
+// first elements are listed in `a.offsets`.  One launch runs every tile of
+// the single-pass classes and of pass 1; a second launch runs pass 2.  Each
+// launch is persistent: workgroups walk a work list of tiles ordered by
+// class, longest lines first, with the same XCD-contiguous mapping as the
+// pass kernels.  All classes use 512-thread tiles, 16 values per thread,
+// radix 16 and the split exchange.
+struct RaggedClass {
+    PassArgs a;          // in, out and the conjugation are set per launch
+    int32_t kind, log2N; // kernel shape of the class
+    int64_t item_begin;  // first work item (tile) of the class in its launch
+};
+
+constexpr int RAGGED_THREADS = 512;
+constexpr int RAGGED_P1_MIN = 7, RAGGED_P2_MIN = 6; // shortest lift lines (t >= 13)
+
+// One call per tile: a separate function per kernel shape keeps each shape's
+// register allocation to itself (inlined together they spill).
+template <typename Real, int KIND, int L>
+__device__ __attribute__((noinline)) void ragged_tile(const PassArgs &a, int64_t t, unsigned char *smem) {
+    constexpr int LMIN = KIND == K_SINGLE ? 1 : KIND == K_PASS1 ? RAGGED_P1_MIN : RAGGED_P2_MIN;
+    if constexpr (L >= LMIN && L <= MAX_LOG2_LINE) {
+        const Tile<Real, (1 << L), 16, KIND, 16, true> w(a, smem);
+        w.run_one(t);
+    }
+}
+
+template <typename Real, int KIND, int... L>
+__device__ __forceinline__ void ragged_dispatch(int log2N, const PassArgs &a, int64_t t, unsigned char *smem,
+                                                std::integer_sequence<int, L...>) {
+    (void)((log2N == L ? (ragged_tile<Real, KIND, L>(a, t, smem), 0) : 0) + ...);
+}
+
+// Register budget: 128 VGPRs for complex64 (two 512-thread workgroups per
+// CU at least), 256 for complex128.
+template <typename Real> constexpr int ragged_min_waves() { return sizeof(Real) == 4 ? 4 : 2; }
+
+// A workgroup-uniform record read from memory, word by word through
+// readfirstlane, so that its fields live in scalar registers.
+template <typename T> __device__ __forceinline__ T uniform_copy(const T *src) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized record");
+    T r;
+    const int *w = reinterpret_cast<const int *>(src);
+    int *d = reinterpret_cast<int *>(&r);
+#pragma unroll
+    for (int i = 0; i < int(sizeof(T) / 4); ++i) d[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    return r;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(RAGGED_THREADS, (ragged_min_waves<Real>())) void ragged_kernel(const RaggedClass *__restrict__ cls, int ncls,
+                                                                int64_t items, const void *in, void *out, int inv) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int64_t G = gridDim.x, g = blockIdx.x;
+    const int64_t rank = (G & 7) == 0 ? (g & 7) * (G >> 3) + (g >> 3) : g;
+    for (int64_t it0 = 0; it0 < items; it0 += G) { // the exit test is workgroup-uniform
+        const int64_t it = it0 + rank;
+        if (it >= items) break;
+        int k = 0;
+        while (k + 1 < ncls && __builtin_amdgcn_readfirstlane(int(cls[k + 1].item_begin <= it))) ++k;
+        const RaggedClass rc = uniform_copy(&cls[k]);
+        PassArgs a = rc.a;
+        const int kind = rc.kind, log2N = rc.log2N;
+        if (kind != K_PASS2) a.in = in;   // pass 2 reads the scratch array
+        if (kind != K_PASS1) a.out = out; // pass 1 writes it
+        a.conj_in = kind != K_PASS2 ? inv : 0;
+        a.conj_out = kind != K_PASS1 ? inv : 0;
+        const int64_t t = it - rc.item_begin;
+        __syncthreads(); // the previous tile's LDS readers are done
+        constexpr auto seq = std::make_integer_sequence<int, MAX_LOG2_LINE + 1>{};
+        if (kind == K_SINGLE) ragged_dispatch<Real, K_SINGLE>(log2N, a, t, smem_raw, seq);
+        else if (kind == K_PASS1) ragged_dispatch<Real, K_PASS1>(log2N, a, t, smem_raw, seq);
+        else ragged_dispatch<Real, K_PASS2>(log2N, a, t, smem_raw, seq);
     }
 }
 
@@ -500,6 +583,30 @@ struct fft_plan {
     size_t table_bytes = 0;
     const void *tw1 = nullptr, *tw2 = nullptr, *tw_hi = nullptr, *tw_lo = nullptr;
     Launch k1, k2;
+    int64_t total = 0; // elements in the input (and output) buffer
+    // Packed batch of uneven lengths: two persistent launches over classes
+    // of equal length, replayed as one captured graph per (in, out, sign).
+    struct RaggedLaunch {
+        int nclass = 0;
+        int64_t items = 0, grid = 0;
+        size_t lds = 0;
+        const void *cls = nullptr; // device array of classes
+    };
+    bool ragged = false;
+    int length_classes = 0;
+    RaggedLaunch ra, rb;
+    void *meta = nullptr; // device: classes and transform offsets
+    size_t meta_bytes = 0;
+    bool use_graph = false;
+    hipStream_t cap = nullptr; // private stream for graph capture
+    struct GraphEntry {
+        const void *in;
+        void *out;
+        int sign;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
     // Benchmark timing: a ring of event triples (before pass 1, after pass 1,
     // after pass 2) recorded on the execute stream; drained on read.
     bool timing = false;
@@ -658,9 +765,89 @@ void free_plan(fft_plan *p) {
     if (!p) return;
     for (auto &e : p->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &g : p->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    if (p->cap) (void)hipStreamDestroy(p->cap);
     if (p->scratch) (void)hipFree(p->scratch);
     if (p->tables) (void)hipFree(p->tables);
+    if (p->meta) (void)hipFree(p->meta);
     delete p;
+}
+
+int launch_ragged(const fft_plan *p, const fft_plan::RaggedLaunch &R, const void *in, void *out, int inv,
+                  hipStream_t st) {
+    if (R.items <= 0) return FFT_OK;
+    const RaggedClass *cls = static_cast<const RaggedClass *>(R.cls);
+    if (p->dtype == FFT_C64)
+        hipLaunchKernelGGL(ragged_kernel<float>, dim3(unsigned(R.grid)), dim3(RAGGED_THREADS), R.lds, st, cls,
+                           R.nclass, R.items, in, out, inv);
+    else
+        hipLaunchKernelGGL(ragged_kernel<double>, dim3(unsigned(R.grid)), dim3(RAGGED_THREADS), R.lds, st, cls,
+                           R.nclass, R.items, in, out, inv);
+    return hipGetLastError() == hipSuccess ? FFT_OK : FFT_E_HIP;
+}
+
+constexpr size_t MAX_GRAPHS = 16; // captured graphs kept per plan
+
+// The two launches of a packed uneven batch, as one graph launch when
+// possible: a graph is captured on the plan's private stream the first time
+// an (in, out, sign) triple is seen and replayed afterwards.  When the
+// caller's stream is itself being captured, or the cache is full, the
+// kernels are launched directly.  `ev` (optional) brackets the work.
+int execute_ragged(fft_plan *p, const void *in, void *out, int sign, hipStream_t st, hipEvent_t *ev) {
+    const int inv = sign > 0;
+    bool graph = p->use_graph;
+    if (graph) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+            (void)hipGetLastError();
+            graph = false;
+        } else if (cs != hipStreamCaptureStatusNone) {
+            graph = false;
+        }
+    }
+    if (graph) {
+        const fft_plan::GraphEntry *hit = nullptr;
+        for (const auto &g : p->graphs)
+            if (g.in == in && g.out == out && g.sign == sign) hit = &g;
+        if (!hit && p->graphs.size() < MAX_GRAPHS) {
+            if (!p->cap && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
+                (void)hipGetLastError();
+                p->cap = nullptr;
+            }
+            if (p->cap && hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                int rc = launch_ragged(p, p->ra, in, out, inv, p->cap);
+                if (rc == FFT_OK) rc = launch_ragged(p, p->rb, in, out, inv, p->cap);
+                hipGraph_t g = nullptr;
+                const bool ended = hipStreamEndCapture(p->cap, &g) == hipSuccess;
+                hipGraphExec_t e = nullptr;
+                if (rc == FFT_OK && ended && g && hipGraphInstantiate(&e, g, nullptr, nullptr, 0) == hipSuccess) {
+                    p->graphs.push_back({in, out, sign, g, e});
+                    hit = &p->graphs.back();
+                } else {
+                    (void)hipGetLastError();
+                    if (g) (void)hipGraphDestroy(g);
+                }
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+        if (hit) {
+            if (ev && hipEventRecord(ev[0], st) != hipSuccess) return FFT_E_HIP;
+            if (hipGraphLaunch(hit->exec, st) != hipSuccess) return FFT_E_HIP;
+            if (ev && (hipEventRecord(ev[1], st) != hipSuccess || hipEventRecord(ev[2], st) != hipSuccess))
+                return FFT_E_HIP;
+            return FFT_OK;
+        }
+    }
+    if (ev && hipEventRecord(ev[0], st) != hipSuccess) return FFT_E_HIP;
+    int rc = launch_ragged(p, p->ra, in, out, inv, st);
+    if (rc == FFT_OK && ev) rc = hipEventRecord(ev[1], st) == hipSuccess ? FFT_OK : FFT_E_HIP;
+    if (rc == FFT_OK) rc = launch_ragged(p, p->rb, in, out, inv, st);
+    if (rc == FFT_OK && ev) rc = hipEventRecord(ev[2], st) == hipSuccess ? FFT_OK : FFT_E_HIP;
+    return rc;
 }
 
 int launch(const fft_plan *p, const Launch &L, const PassArgs &args, hipStream_t st) {
@@ -736,6 +923,7 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
     if (!p) return FFT_E_OOM;
     p->n = n;
     p->batch = batch;
+    p->total = n * batch;
     p->dtype = dtype;
     p->log2n = t;
     p->radix = radix;
@@ -844,6 +1032,241 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out) {
     return fft_plan_create_ex(n, batch, dtype, nullptr, plan_out);
 }
 
+int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const fft_plan_opts *opts,
+                         fft_plan **plan_out) {
+    if (!plan_out) return FFT_E_NULL;
+    *plan_out = nullptr;
+    if (!lengths) return FFT_E_NULL;
+    if (dtype != FFT_C64 && dtype != FFT_C128) return FFT_E_DTYPE;
+    if (count < 1) return FFT_E_SIZE;
+    fft_plan_opts o;
+    memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    if (o.log2_p || (o.radix && o.radix != 16) || o.lines_per_block || o.lines_per_block2 ||
+        o.values_per_thread || o.reserved[0] || o.reserved[1] || (o.flags & ~int32_t(FFT_OPT_NO_GRAPH)))
+        return FFT_E_ARG;
+    const size_t esize = dtype == FFT_C64 ? 8 : 16;
+    const int max_t = dtype == FFT_C64 ? FFT_MAX_LOG2N_C64 : FFT_MAX_LOG2N_C128;
+    // Lengths, packed offsets and the classes of equal length.
+    std::vector<std::vector<int64_t>> by_t(max_t + 1);
+    int64_t total = 0;
+    bool unsupported = false;
+    for (int64_t i = 0; i < count; ++i) {
+        const int t = ilog2_exact(lengths[i]);
+        if (t < 1) return FFT_E_SIZE;
+        if (t > max_t) {
+            unsupported = true;
+            continue;
+        }
+        by_t[t].push_back(total);
+        total += lengths[i];
+        if (total > (int64_t(1) << 40)) return FFT_E_SIZE;
+    }
+    if (unsupported) return FFT_E_UNSUPPORTED;
+    // Single-pass tiles address the packed buffer through one 32-bit
+    // buffer descriptor.
+    if (uint64_t(total) * esize > uint64_t(UINT32_MAX)) return FFT_E_UNSUPPORTED;
+
+    fft_plan *p = new (std::nothrow) fft_plan;
+    if (!p) return FFT_E_OOM;
+    p->ragged = true;
+    p->n = total;
+    p->batch = count;
+    p->total = total;
+    p->dtype = dtype;
+    p->esize = esize;
+    p->radix = 16;
+    p->use_graph = !(o.flags & FFT_OPT_NO_GRAPH);
+    auto fail = [&](int rc) {
+        free_plan(p);
+        return rc;
+    };
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FFT_E_HIP);
+    }
+
+    // Twiddle tables: w_N^e for each line length used, and the two-level
+    // inter-pass tables of each lifted length.
+    const int lsize = int(esize / 2), csize = int(esize);
+    struct ClassSpec {
+        int kind, log2N, t, log2T, log2W, pitch;
+        int64_t lines, tiles, count;
+        int64_t lds;
+        size_t off_index; // first entry of the class's offsets
+    };
+    std::vector<ClassSpec> A, B;
+    std::vector<int64_t> offsets;
+    bool used_line[MAX_LOG2_LINE + 1] = {};
+    bool two_pass = false;
+    auto tile_lines = [](int log2N) {
+        const int N = 1 << log2N;
+        return RAGGED_THREADS / (N / vals_per_thread(N));
+    };
+    auto spec = [&](int kind, int log2N, int t, int64_t lines, int log2W, size_t off_index, int64_t cnt) {
+        ClassSpec c;
+        const int N = 1 << log2N, T = tile_lines(log2N), E = vals_per_thread(N);
+        c.kind = kind;
+        c.log2N = log2N;
+        c.t = t;
+        c.log2T = ilog2_exact(T);
+        c.log2W = kind == K_SINGLE ? c.log2T : log2W;
+        c.pitch = exchange_pitch(N, T, N / E, lsize, kind != K_SINGLE);
+        c.lines = lines;
+        c.tiles = (lines + T - 1) / T;
+        c.count = cnt;
+        c.lds = lds_bytes(N, 16, T, E, c.pitch, lsize, csize, kind == K_PASS1);
+        c.off_index = off_index;
+        used_line[log2N] = true;
+        return c;
+    };
+    int classes = 0;
+    for (int t = max_t; t >= 1; --t) { // longest lines first
+        if (by_t[t].empty()) continue;
+        ++classes;
+        const size_t oi = offsets.size();
+        offsets.insert(offsets.end(), by_t[t].begin(), by_t[t].end());
+        const int64_t cnt = int64_t(by_t[t].size());
+        if (t <= MAX_LOG2_LINE) {
+            A.push_back(spec(K_SINGLE, t, t, cnt, 0, oi, cnt));
+        } else {
+            two_pass = true;
+            const int lq = (t + 1) / 2, lp = t - lq;
+            // Scratch slabs W = min(T1, TPL2) wide: pass 2 reads them with a
+            // separable offset.
+            const int T1 = tile_lines(lq), tpl2 = (1 << lp) / vals_per_thread(1 << lp);
+            const int lW = ilog2_exact(T1 < tpl2 ? T1 : tpl2);
+            A.push_back(spec(K_PASS1, lq, t, cnt << lp, lW, oi, cnt));
+            B.push_back(spec(K_PASS2, lp, t, cnt << lq, lW, oi, cnt));
+        }
+    }
+    p->length_classes = classes;
+    p->passes = two_pass ? 2 : 1;
+
+    // Device memory: tables, scratch (two-pass classes), classes + offsets.
+    std::vector<int64_t> tab_off(MAX_LOG2_LINE + 1, -1);
+    std::vector<int64_t> hi_off(max_t + 1, -1), lo_off(max_t + 1, -1);
+    int64_t entries = 0;
+    for (int L = 1; L <= MAX_LOG2_LINE; ++L)
+        if (used_line[L]) {
+            tab_off[L] = entries;
+            entries += int64_t(1) << L;
+        }
+    for (int t = MAX_LOG2_LINE + 1; t <= max_t; ++t)
+        if (!by_t[t].empty()) {
+            const int h = (t + 1) / 2;
+            hi_off[t] = entries;
+            entries += int64_t(1) << (t - h);
+            lo_off[t] = entries;
+            entries += int64_t(1) << h;
+        }
+    p->table_bytes = size_t(entries) * esize;
+    if (hipMalloc(&p->tables, p->table_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p->tables = nullptr;
+        return fail(FFT_E_OOM);
+    }
+    if (two_pass) {
+        p->scratch_bytes = size_t(total) * esize;
+        if (hipMalloc(&p->scratch, p->scratch_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p->scratch = nullptr;
+            return fail(FFT_E_OOM);
+        }
+    }
+    const size_t ncls = A.size() + B.size();
+    p->meta_bytes = ncls * sizeof(RaggedClass) + offsets.size() * sizeof(int64_t);
+    if (hipMalloc(&p->meta, p->meta_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p->meta = nullptr;
+        return fail(FFT_E_OOM);
+    }
+    char *tb = static_cast<char *>(p->tables);
+    int rc = FFT_OK;
+    for (int L = 1; L <= MAX_LOG2_LINE && rc == FFT_OK; ++L)
+        if (tab_off[L] >= 0) rc = gen_table(dtype, tb + tab_off[L] * esize, int64_t(1) << L, 1, L);
+    for (int t = MAX_LOG2_LINE + 1; t <= max_t && rc == FFT_OK; ++t)
+        if (hi_off[t] >= 0) {
+            const int h = (t + 1) / 2;
+            rc = gen_table(dtype, tb + hi_off[t] * esize, int64_t(1) << (t - h), int64_t(1) << h, t);
+            if (rc == FFT_OK) rc = gen_table(dtype, tb + lo_off[t] * esize, int64_t(1) << h, 1, t);
+        }
+    if (rc != FFT_OK) return fail(rc);
+
+    // Class records.
+    char *meta = static_cast<char *>(p->meta);
+    const int64_t *dev_offsets = reinterpret_cast<const int64_t *>(meta + ncls * sizeof(RaggedClass));
+    std::vector<RaggedClass> recs(ncls);
+    auto fill = [&](const ClassSpec &c, RaggedClass &r, int64_t item_begin) {
+        memset(&r, 0, sizeof(r));
+        r.kind = c.kind;
+        r.log2N = c.log2N;
+        r.item_begin = item_begin;
+        PassArgs &a = r.a;
+        a.tw = tb + tab_off[c.log2N] * esize;
+        a.lines = c.lines;
+        a.ntiles = c.tiles;
+        a.log2T = c.log2T;
+        a.log2T1 = c.log2W;
+        a.pitch = c.pitch;
+        a.offsets = dev_offsets + c.off_index;
+        a.total = total;
+        if (c.kind == K_SINGLE) {
+            a.n = int64_t(1) << c.t;
+        } else {
+            const int lq = (c.t + 1) / 2;
+            a.n = int64_t(1) << c.t;
+            a.log2q = lq;
+            a.log2p = c.t - lq;
+            a.log2h = lq;
+            a.tw_hi = tb + hi_off[c.t] * esize;
+            a.tw_lo = tb + lo_off[c.t] * esize;
+            if (c.kind == K_PASS1) a.out = p->scratch;
+            else a.in = p->scratch;
+        }
+    };
+    auto build_launch = [&](std::vector<ClassSpec> &cs, size_t first, fft_plan::RaggedLaunch &R) -> int {
+        R.nclass = int(cs.size());
+        R.cls = meta + first * sizeof(RaggedClass);
+        int64_t items = 0, lds = 0;
+        for (size_t k = 0; k < cs.size(); ++k) {
+            fill(cs[k], recs[first + k], items);
+            items += cs[k].tiles;
+            if (cs[k].lds > lds) lds = cs[k].lds;
+        }
+        R.items = items;
+        R.lds = size_t(lds);
+        if (items == 0) return FFT_OK;
+        if (lds > LDS_BUDGET) return FFT_E_UNSUPPORTED;
+        const void *fn = dtype == FFT_C64 ? reinterpret_cast<const void *>(&ragged_kernel<float>)
+                                          : reinterpret_cast<const void *>(&ragged_kernel<double>);
+        int per_cu = 0, cus = 0;
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(LDS_BUDGET)) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, RAGGED_THREADS, R.lds) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) {
+            (void)hipGetLastError();
+            return FFT_E_HIP;
+        }
+        if (per_cu < 1) return FFT_E_UNSUPPORTED;
+        const int64_t resident = int64_t(per_cu) * cus;
+        R.grid = items < resident ? items : resident;
+        if (R.grid >= 8) R.grid &= ~int64_t(7);
+        return FFT_OK;
+    };
+    rc = build_launch(A, 0, p->ra);
+    if (rc == FFT_OK) rc = build_launch(B, A.size(), p->rb);
+    if (rc != FFT_OK) return fail(rc);
+    if (hipMemcpy(meta, recs.data(), ncls * sizeof(RaggedClass), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(meta + ncls * sizeof(RaggedClass), offsets.data(), offsets.size() * sizeof(int64_t),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FFT_E_HIP);
+    }
+    *plan_out = p;
+    return FFT_OK;
+}
+
 int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void *stream) {
     if (!plan || !in || !out) return FFT_E_NULL;
     if (sign != -1 && sign != 1) return FFT_E_SIGN;
@@ -853,7 +1276,7 @@ int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void 
     {
         // Partial overlap of in and out is not allowed (exact aliasing is).
         const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
-        const uintptr_t bytes = uintptr_t(plan->n) * uintptr_t(plan->batch) * plan->esize;
+        const uintptr_t bytes = uintptr_t(plan->total) * plan->esize;
         if (a != b && a < b + bytes && b < a + bytes) return FFT_E_ARG;
     }
     fft_plan *p = const_cast<fft_plan *>(plan);
@@ -878,9 +1301,11 @@ int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void 
             --p->ring_count;
         }
         ev = &p->ev[size_t(p->ring_head) * 3];
-        if (rc == FFT_OK) rc = hipEventRecord(ev[0], st) == hipSuccess ? FFT_OK : FFT_E_HIP;
+        if (rc == FFT_OK && !p->ragged) rc = hipEventRecord(ev[0], st) == hipSuccess ? FFT_OK : FFT_E_HIP;
     }
-    if (p->passes == 1) {
+    if (p->ragged) {
+        if (rc == FFT_OK) rc = execute_ragged(p, in, out, sign, st, ev);
+    } else if (p->passes == 1) {
         a.in = in;
         a.out = out;
         a.tw = p->tw1;
@@ -956,6 +1381,18 @@ int fft_plan_get_info(const fft_plan *p, fft_plan_info *info) {
     info->table_bytes = int64_t(p->table_bytes);
     info->variant_pass1 = p->k1.var.code();
     info->variant_pass2 = p->passes == 2 ? p->k2.var.code() : 0;
+    if (p->ragged) {
+        info->lines_per_block_pass1 = info->lines_per_block_pass2 = 0;
+        info->grid_pass1 = int32_t(p->ra.grid);
+        info->grid_pass2 = int32_t(p->rb.grid);
+        info->threads_pass1 = p->ra.items ? RAGGED_THREADS : 0;
+        info->threads_pass2 = p->rb.items ? RAGGED_THREADS : 0;
+        info->lds_bytes_pass1 = int64_t(p->ra.lds);
+        info->lds_bytes_pass2 = int64_t(p->rb.lds);
+        info->variant_pass1 = info->variant_pass2 = 2;
+        info->length_classes = p->length_classes;
+        info->graph_launch = p->use_graph ? 1 : 0;
+    }
     return FFT_OK;
 }
 

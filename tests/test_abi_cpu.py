@@ -43,7 +43,10 @@ def test_binding_lists_match_header():
 
 
 def test_abi_version():
-    assert _lib().fft_abi_version() == 101
+    import re
+    with open(HEADER) as f:
+        declared = int(re.search(r"#define LIFTFFT_ABI_VERSION (\d+)", f.read()).group(1))
+    assert _lib().fft_abi_version() == declared
 
 
 def test_strerror_covers_codes():
@@ -98,3 +101,30 @@ def test_null_plan_paths():
     assert L.fft_plan_destroy(None) == 0
     assert L.fft_plan_get_info(None, None) == -4
     assert L.fft_plan_set_timing(None, 1) == -4
+
+
+def test_create_many_validation():
+    """Argument checks of fft_plan_create_many (all host-side, before any
+    device work)."""
+    from paper_0811_2535_amd.binding import PlanOpts
+    L = _lib()
+
+    def arr(*v):
+        return (ctypes.c_int64 * len(v))(*v)
+
+    h = ctypes.c_void_p(123)
+    assert L.fft_plan_create_many(None, 1, 0, None, ctypes.byref(h)) == -4
+    assert L.fft_plan_create_many(arr(8), 1, 0, None, None) == -4
+    assert L.fft_plan_create_many(arr(8), 0, 0, None, ctypes.byref(h)) == -1
+    assert h.value is None
+    assert L.fft_plan_create_many(arr(8), 1, 7, None, ctypes.byref(h)) == -2
+    for bad in ((8, 12), (8, 1), (8, 0), (8, -16)):
+        assert L.fft_plan_create_many(arr(*bad), 2, 0, None, ctypes.byref(h)) == -1, bad
+    assert L.fft_plan_create_many(arr(8, 1 << 25), 2, 0, None, ctypes.byref(h)) == -8
+    assert L.fft_plan_create_many(arr(8, 1 << 25), 2, 1, None, ctypes.byref(h)) == -8
+    # the packed buffer must stay below 2^32 bytes (32-bit buffer descriptors)
+    big = arr(*([1 << 24] * 32))
+    assert L.fft_plan_create_many(big, 32, 0, None, ctypes.byref(h)) == -8
+    for opts in (PlanOpts(0, 2, 0), PlanOpts(3, 0, 0), PlanOpts(0, 0, 4), PlanOpts(0, 0, 0, 2),
+                 PlanOpts(0, 0, 0, 0, 1), PlanOpts(0, 0, 0, 0, 2), PlanOpts(0, 0, 0, 0, 0, 16)):
+        assert L.fft_plan_create_many(arr(8, 16), 2, 0, ctypes.byref(opts), ctypes.byref(h)) == -9
