@@ -190,6 +190,86 @@ def measure_fwd_bwd(torch, lf, datagen, reps: int = 5) -> dict:
             "hbm_gbps_ffts": round(2 * 32 * n * batch / (fft_ms_ad * 1e-3) / 1e9, 1)}
 
 
+def measure_ragged(torch, lf, datagen, reps: int = 10) -> dict:
+    """Batched uneven lengths: 4096 complex64 transforms with k ~ U{8..16}
+    (seed 3), U[-1,1], packed back to back; the plan's graph launch against
+    (a) one single-length batched plan per length class (each class gathered
+    into its own contiguous buffer beforehand, not timed) and (b) one plain
+    launch per transform."""
+    import numpy as np
+    ks = datagen.uneven_log2_lengths(4096, 8, 16, seed=3)
+    lengths = [1 << int(k) for k in ks]
+    total = sum(lengths)
+    dev = torch.device("cuda:0")
+    x_np = datagen.ragged_signals(lengths, np.complex64, "uniform", 3)
+    sets = 3  # rotated so that no input is still in the last-level cache
+    xs = [torch.from_numpy(x_np).to(dev) for _ in range(sets)]
+    ys = [torch.empty_like(xs[0]) for _ in range(sets)]
+    plan = lf.Plan.uneven(lengths, torch.complex64, graph=True)
+    for i in range(sets):
+        plan.execute(xs[i], ys[i], -1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(reps):
+        plan.execute(xs[i % sets], ys[i % sets], -1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / reps
+    info = plan.info()
+    plan.destroy()
+
+    # (a) per-class batched plans on contiguous class buffers.
+    offs = np.concatenate([[0], np.cumsum(lengths)[:-1]])
+    classes = {}
+    for i, ln in enumerate(lengths):
+        classes.setdefault(ln, []).append(i)
+    cls_bufs = []
+    for ln, idx in sorted(classes.items(), reverse=True):
+        block = np.stack([x_np[offs[i]:offs[i] + ln] for i in idx])
+        xb = [torch.from_numpy(block).to(dev) for _ in range(sets)]
+        yb = [torch.empty_like(xb[0]) for _ in range(sets)]
+        cls_bufs.append((lf.Plan(ln, len(idx), torch.complex64), xb, yb))
+    for pl, xb, yb in cls_bufs:
+        pl.execute(xb[0], yb[0], -1)
+    torch.cuda.synchronize()
+    e0.record()
+    for i in range(reps):
+        for pl, xb, yb in cls_bufs:
+            pl.execute(xb[i % sets], yb[i % sets], -1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_classes = e0.elapsed_time(e1) / reps
+    for pl, _, _ in cls_bufs:
+        pl.destroy()
+    del cls_bufs
+
+    # (b) one launch per transform (views into the packed buffers).
+    plans = {ln: lf.Plan(ln, 1, torch.complex64) for ln in classes}
+    views = [(plans[ln], int(o), ln) for o, ln in zip(offs, lengths)]
+    torch.cuda.synchronize()
+    e0.record()
+    for pl, o, ln in views:
+        pl.execute(xs[0][o:o + ln], ys[0][o:o + ln], -1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_each = e0.elapsed_time(e1)
+    for pl in plans.values():
+        pl.destroy()
+    flops = sum(5.0 * ln * math.log2(ln) for ln in lengths)
+    alg_bytes = sum((16 if ln <= 4096 else 32) * ln for ln in lengths)
+    return {"workload": "4096 c64 transforms, n = 2^k with k ~ U{8..16} (seed 3), packed, forward",
+            "elements": total, "length_classes": info["length_classes"],
+            "ms_graph": round(ms_graph, 4),
+            "gflops": round(flops / (ms_graph * 1e-3) / 1e9, 1),
+            "hbm_gbps_algorithmic": round(alg_bytes / (ms_graph * 1e-3) / 1e9, 1),
+            "ms_per_class_batched_plans": round(ms_classes, 4),
+            "ms_one_launch_per_transform": round(ms_each, 4),
+            "speedup_vs_per_class": round(ms_classes / ms_graph, 3),
+            "speedup_vs_per_transform": round(ms_each / ms_graph, 3),
+            "grid": [info["grid_pass1"], info["grid_pass2"]]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,7 +279,7 @@ def main() -> int:
     ap.add_argument("--sets", type=int, default=4, help="buffer sets rotated between transforms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the differentiation-form measurement")
+                    help="skip the differentiation-form and uneven-batch measurements")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary from two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of this benchmark and exit")
@@ -358,6 +438,8 @@ def main() -> int:
         del xs, ys
         result["fwd_bwd"] = measure_fwd_bwd(torch, lf, datagen)
         lf.clear_plan_cache()
+        print("[bench] batched uneven lengths, 4096 transforms", file=sys.stderr, flush=True)
+        result["ragged"] = measure_ragged(torch, lf, datagen)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (FP64 oracle, 1 thread)", file=sys.stderr, flush=True)
         base, parity = cpu_baseline(host_inputs[0], host_inputs[1], y0, y1)

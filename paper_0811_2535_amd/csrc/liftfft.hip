@@ -382,14 +382,14 @@ __global__ __launch_bounds__((max_threads<Real, EMAX, PERSIST>()), (min_waves<DE
 
 // ---------------------------------------------------------------------------
 // Packed batches of uneven power-of-two lengths.  The plan groups the
-// transforms into classes of equal length; a class describes one kernel shape
-// (single pass, or pass 1 / pass 2 of the lift) over its transforms, whose
-// first elements are listed in `a.offsets`.  One launch runs every tile of
-// the single-pass classes and of pass 1; a second launch runs pass 2.  Each
-// launch is persistent: workgroups walk a work list of tiles ordered by
-// class, longest lines first, with the same XCD-contiguous mapping as the
-// pass kernels.  All classes use 512-thread tiles, 16 values per thread,
-// radix 16 and the split exchange.
+// transforms into classes of equal length.  Lengths up to 2^12 run through
+// the single-pass kernel, one launch per class, with `a.offsets` listing
+// each transform's first element.  The lifted lengths share two persistent
+// launches (pass 1 of every lifted class, then pass 2 of every lifted
+// class): workgroups walk a work list of tiles ordered by class, longest
+// lines first, with the same XCD-contiguous mapping as the pass kernels.
+// The lifted classes use 512-thread tiles, 16 values per thread, radix 16
+// and the split exchange.
 struct RaggedClass {
     PassArgs a;          // in, out and the conjugation are set per launch
     int32_t kind, log2N; // kernel shape of the class
@@ -399,11 +399,9 @@ struct RaggedClass {
 constexpr int RAGGED_THREADS = 512;
 constexpr int RAGGED_P1_MIN = 7, RAGGED_P2_MIN = 6; // shortest lift lines (t >= 13)
 
-// One call per tile: a separate function per kernel shape keeps each shape's
-// register allocation to itself (inlined together they spill).
 template <typename Real, int KIND, int L>
-__device__ __attribute__((noinline)) void ragged_tile(const PassArgs &a, int64_t t, unsigned char *smem) {
-    constexpr int LMIN = KIND == K_SINGLE ? 1 : KIND == K_PASS1 ? RAGGED_P1_MIN : RAGGED_P2_MIN;
+__device__ __forceinline__ void ragged_tile(const PassArgs &a, int64_t t, unsigned char *smem) {
+    constexpr int LMIN = KIND == K_PASS1 ? RAGGED_P1_MIN : RAGGED_P2_MIN;
     if constexpr (L >= LMIN && L <= MAX_LOG2_LINE) {
         const Tile<Real, (1 << L), 16, KIND, 16, true> w(a, smem);
         w.run_one(t);
@@ -446,15 +444,14 @@ __global__ __launch_bounds__(RAGGED_THREADS, (ragged_min_waves<Real>())) void ra
         const RaggedClass rc = uniform_copy(&cls[k]);
         PassArgs a = rc.a;
         const int kind = rc.kind, log2N = rc.log2N;
-        if (kind != K_PASS2) a.in = in;   // pass 2 reads the scratch array
-        if (kind != K_PASS1) a.out = out; // pass 1 writes it
-        a.conj_in = kind != K_PASS2 ? inv : 0;
-        a.conj_out = kind != K_PASS1 ? inv : 0;
+        if (kind == K_PASS1) a.in = in;   // pass 2 reads the scratch array
+        if (kind == K_PASS2) a.out = out; // pass 1 writes it
+        a.conj_in = kind == K_PASS1 ? inv : 0;
+        a.conj_out = kind == K_PASS2 ? inv : 0;
         const int64_t t = it - rc.item_begin;
         __syncthreads(); // the previous tile's LDS readers are done
         constexpr auto seq = std::make_integer_sequence<int, MAX_LOG2_LINE + 1>{};
-        if (kind == K_SINGLE) ragged_dispatch<Real, K_SINGLE>(log2N, a, t, smem_raw, seq);
-        else if (kind == K_PASS1) ragged_dispatch<Real, K_PASS1>(log2N, a, t, smem_raw, seq);
+        if (kind == K_PASS1) ragged_dispatch<Real, K_PASS1>(log2N, a, t, smem_raw, seq);
         else ragged_dispatch<Real, K_PASS2>(log2N, a, t, smem_raw, seq);
     }
 }
@@ -595,6 +592,11 @@ struct fft_plan {
     bool ragged = false;
     int length_classes = 0;
     RaggedLaunch ra, rb;
+    struct SingleClass {
+        Launch L;
+        PassArgs a; // in, out and the conjugation are set per execute
+    };
+    std::vector<SingleClass> singles;
     void *meta = nullptr; // device: classes and transform offsets
     size_t meta_bytes = 0;
     bool use_graph = false;
@@ -761,6 +763,13 @@ int drain_all(fft_plan *p) {
     return rc;
 }
 
+int launch(const fft_plan *p, const Launch &L, const PassArgs &args, hipStream_t st) {
+    if (L.grid <= 0) return FFT_OK;
+    hipLaunchKernelGGL(L.fn, dim3(unsigned(L.grid)), dim3(unsigned(L.threads)), L.lds, st, args);
+    (void)p;
+    return hipGetLastError() == hipSuccess ? FFT_OK : FFT_E_HIP;
+}
+
 void free_plan(fft_plan *p) {
     if (!p) return;
     for (auto &e : p->ev)
@@ -787,6 +796,24 @@ int launch_ragged(const fft_plan *p, const fft_plan::RaggedLaunch &R, const void
         hipLaunchKernelGGL(ragged_kernel<double>, dim3(unsigned(R.grid)), dim3(RAGGED_THREADS), R.lds, st, cls,
                            R.nclass, R.items, in, out, inv);
     return hipGetLastError() == hipSuccess ? FFT_OK : FFT_E_HIP;
+}
+
+// Every launch of a packed uneven batch in order: pass 1 of the lifted
+// classes, the single-pass classes, then (after `ev_mid`, if given) pass 2
+// of the lifted classes.
+int ragged_sequence(const fft_plan *p, const void *in, void *out, int inv, hipStream_t st, hipEvent_t ev_mid) {
+    int rc = launch_ragged(p, p->ra, in, out, inv, st);
+    for (const auto &sc : p->singles) {
+        if (rc != FFT_OK) break;
+        PassArgs a = sc.a;
+        a.in = in;
+        a.out = out;
+        a.conj_in = a.conj_out = inv;
+        rc = launch(p, sc.L, a, st);
+    }
+    if (rc == FFT_OK && ev_mid) rc = hipEventRecord(ev_mid, st) == hipSuccess ? FFT_OK : FFT_E_HIP;
+    if (rc == FFT_OK) rc = launch_ragged(p, p->rb, in, out, inv, st);
+    return rc;
 }
 
 constexpr size_t MAX_GRAPHS = 16; // captured graphs kept per plan
@@ -818,8 +845,7 @@ int execute_ragged(fft_plan *p, const void *in, void *out, int sign, hipStream_t
                 p->cap = nullptr;
             }
             if (p->cap && hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-                int rc = launch_ragged(p, p->ra, in, out, inv, p->cap);
-                if (rc == FFT_OK) rc = launch_ragged(p, p->rb, in, out, inv, p->cap);
+                const int rc = ragged_sequence(p, in, out, inv, p->cap, nullptr);
                 hipGraph_t g = nullptr;
                 const bool ended = hipStreamEndCapture(p->cap, &g) == hipSuccess;
                 hipGraphExec_t e = nullptr;
@@ -843,19 +869,11 @@ int execute_ragged(fft_plan *p, const void *in, void *out, int sign, hipStream_t
         }
     }
     if (ev && hipEventRecord(ev[0], st) != hipSuccess) return FFT_E_HIP;
-    int rc = launch_ragged(p, p->ra, in, out, inv, st);
-    if (rc == FFT_OK && ev) rc = hipEventRecord(ev[1], st) == hipSuccess ? FFT_OK : FFT_E_HIP;
-    if (rc == FFT_OK) rc = launch_ragged(p, p->rb, in, out, inv, st);
+    int rc = ragged_sequence(p, in, out, inv, st, ev ? ev[1] : nullptr);
     if (rc == FFT_OK && ev) rc = hipEventRecord(ev[2], st) == hipSuccess ? FFT_OK : FFT_E_HIP;
     return rc;
 }
 
-int launch(const fft_plan *p, const Launch &L, const PassArgs &args, hipStream_t st) {
-    if (L.grid <= 0) return FFT_OK;
-    hipLaunchKernelGGL(L.fn, dim3(unsigned(L.grid)), dim3(unsigned(L.threads)), L.lds, st, args);
-    (void)p;
-    return hipGetLastError() == hipSuccess ? FFT_OK : FFT_E_HIP;
-}
 
 } // namespace
 
@@ -1120,6 +1138,12 @@ int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const
         used_line[log2N] = true;
         return c;
     };
+    struct SingleSpec {
+        int t;
+        int64_t count;
+        size_t off_index;
+    };
+    std::vector<SingleSpec> single_specs;
     int classes = 0;
     for (int t = max_t; t >= 1; --t) { // longest lines first
         if (by_t[t].empty()) continue;
@@ -1128,7 +1152,8 @@ int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const
         offsets.insert(offsets.end(), by_t[t].begin(), by_t[t].end());
         const int64_t cnt = int64_t(by_t[t].size());
         if (t <= MAX_LOG2_LINE) {
-            A.push_back(spec(K_SINGLE, t, t, cnt, 0, oi, cnt));
+            single_specs.push_back({t, cnt, oi});
+            used_line[t] = true;
         } else {
             two_pass = true;
             const int lq = (t + 1) / 2, lp = t - lq;
@@ -1256,6 +1281,24 @@ int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const
     rc = build_launch(A, 0, p->ra);
     if (rc == FFT_OK) rc = build_launch(B, A.size(), p->rb);
     if (rc != FFT_OK) return fail(rc);
+    // Single-pass classes: the tuned single-pass kernel, one launch each.
+    for (const SingleSpec &ss : single_specs) {
+        fft_plan::SingleClass sc;
+        const Variant v;
+        const int l2T = choose_log2T(ss.t, 16, esize, ss.count, 256, 1, 0, K_SINGLE, v);
+        if (!fill_launch(sc.L, dtype, K_SINGLE, ss.t, 16, l2T, ss.count, v, p->device)) return fail(FFT_E_UNSUPPORTED);
+        memset(&sc.a, 0, sizeof(sc.a));
+        sc.a.tw = tb + tab_off[ss.t] * esize;
+        sc.a.lines = ss.count;
+        sc.a.n = int64_t(1) << ss.t;
+        sc.a.ntiles = sc.L.ntiles;
+        sc.a.log2T = sc.a.log2T1 = sc.L.log2T;
+        sc.a.pitch = sc.L.pitch;
+        sc.a.xcd_remap = sc.L.remap;
+        sc.a.offsets = dev_offsets + ss.off_index;
+        sc.a.total = total;
+        p->singles.push_back(sc);
+    }
     if (hipMemcpy(meta, recs.data(), ncls * sizeof(RaggedClass), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(meta + ncls * sizeof(RaggedClass), offsets.data(), offsets.size() * sizeof(int64_t),
                   hipMemcpyHostToDevice) != hipSuccess ||
