@@ -440,6 +440,13 @@ def main() -> int:
         lf.clear_plan_cache()
         print("[bench] batched uneven lengths, 4096 transforms", file=sys.stderr, flush=True)
         result["ragged"] = measure_ragged(torch, lf, datagen)
+        print("[bench] autotuner on the headline shape", file=sys.stderr, flush=True)
+        tplan, tres = lf.Plan.tuned(n, 1, torch.complex64, max_candidates=48)
+        tplan.destroy()
+        result["autotune"] = {"workload": "c64 n=2^%d forward, tuner's own timing" % args.log2n,
+                              "candidates": tres["candidates"], "rejected": tres["rejected"],
+                              "ms_default": round(tres["ms_default"], 4), "ms_tuned": round(tres["ms"], 4),
+                              "chosen": tres["opts"]}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (FP64 oracle, 1 thread)", file=sys.stderr, flush=True)
         base, parity = cpu_baseline(host_inputs[0], host_inputs[1], y0, y1)

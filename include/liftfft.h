@@ -223,8 +223,36 @@ int fft_plan_set_timing(fft_plan *plan, int enable);
 int fft_plan_read_timing(fft_plan *plan, double ms_out[2], int64_t launches_out[2],
                          int reset);
 
+/*
+ * Autotuned plan: the default plan plus up to max_candidates - 1 other
+ * configurations of the same transform (0 = 48) -- other lifts n = p*q and
+ * the single/two-pass threshold, radix 2, the pass-kernel variants and tile
+ * widths -- each timed on device buffers the call allocates (forward
+ * executes on a private stream, about 2 ms of work each) and checked
+ * against the default plan's output (a configuration whose output differs
+ * by more than 1e-4 (complex64) or 1e-10 (complex128) of the largest output
+ * is never chosen).  Returns the fastest as *plan_out; if result is not
+ * NULL it receives that plan's options (fft_plan_create_ex recreates it) and
+ * times.  Tuning is an experiment over implementation variants for one
+ * problem size on one machine (Section 8 of the paper); the outcome is
+ * remembered per (n, batch, dtype, device) for the life of the process, and
+ * a later call with the same shape creates the remembered configuration
+ * without timing.  Synchronous; the device is otherwise idle-assumed (other
+ * work on it skews the timings, not the results).  Errors as
+ * fft_plan_create, plus FFT_E_ARG for max_candidates < 0.
+ */
+typedef struct fft_tune_result {
+    fft_plan_opts opts; /* options of the chosen plan */
+    double ms;          /* chosen plan: milliseconds per forward execute */
+    double ms_default;  /* default plan: milliseconds per forward execute */
+    int32_t candidates; /* configurations timed (the default included) */
+    int32_t rejected;   /* configurations whose output disagreed, or failed */
+} fft_tune_result;
+int fft_plan_create_tuned(int64_t n, int64_t batch, int dtype, int32_t max_candidates, fft_plan **plan_out,
+                          fft_tune_result *result);
+
 /* ABI version of this header (major*100 + minor). */
-#define LIFTFFT_ABI_VERSION 102
+#define LIFTFFT_ABI_VERSION 103
 int fft_abi_version(void);
 
 #ifdef __cplusplus

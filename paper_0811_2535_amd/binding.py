@@ -28,7 +28,7 @@ STATUS = {
 EXPORTED = [
     "fft_plan_create", "fft_plan_create_ex", "fft_execute", "fft_plan_destroy",
     "fft_strerror", "fft_plan_get_info", "fft_plan_set_timing", "fft_plan_read_timing",
-    "fft_abi_version", "fft_plan_create_many",
+    "fft_abi_version", "fft_plan_create_many", "fft_plan_create_tuned",
 ]
 
 
@@ -57,6 +57,19 @@ class PlanOpts(ctypes.Structure):
                 ("lines_per_block", ctypes.c_int32), ("lines_per_block2", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("values_per_thread", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 2)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("opts", PlanOpts), ("ms", ctypes.c_double), ("ms_default", ctypes.c_double),
+                ("candidates", ctypes.c_int32), ("rejected", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        o = self.opts
+        return {"opts": {"log2_p": o.log2_p, "radix": o.radix, "lines_per_block": o.lines_per_block,
+                         "lines_per_block2": o.lines_per_block2, "flags": o.flags,
+                         "values_per_thread": o.values_per_thread},
+                "ms": self.ms, "ms_default": self.ms_default, "candidates": self.candidates,
+                "rejected": self.rejected}
 
 
 class PlanInfo(ctypes.Structure):
@@ -98,6 +111,8 @@ def lib():
                                              ctypes.POINTER(vp)]
             L.fft_plan_create_many.argtypes = [ctypes.POINTER(i64), i64, i32, ctypes.POINTER(PlanOpts),
                                                ctypes.POINTER(vp)]
+            L.fft_plan_create_tuned.argtypes = [i64, i64, i32, ctypes.c_int32, ctypes.POINTER(vp),
+                                                ctypes.POINTER(TuneResult)]
             L.fft_execute.argtypes = [vp, vp, vp, i32, vp]
             L.fft_plan_destroy.argtypes = [vp]
             L.fft_strerror.argtypes = [i32]
@@ -106,7 +121,8 @@ def lib():
             L.fft_plan_set_timing.argtypes = [vp, i32]
             L.fft_plan_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double * 2),
                                                ctypes.POINTER(ctypes.c_int64 * 2), i32]
-            for name in ("fft_plan_create", "fft_plan_create_ex", "fft_plan_create_many", "fft_execute",
+            for name in ("fft_plan_create", "fft_plan_create_ex", "fft_plan_create_many",
+                         "fft_plan_create_tuned", "fft_execute",
                          "fft_plan_destroy", "fft_plan_get_info", "fft_plan_set_timing",
                          "fft_plan_read_timing", "fft_abi_version"):
                 getattr(L, name).restype = i32
@@ -138,6 +154,21 @@ class Plan:
     """A plan for ``batch`` transforms of length ``n`` (owns device memory).
 
     Thin wrapper over fft_plan_create_ex / fft_execute / fft_plan_destroy."""
+
+    @classmethod
+    def tuned(cls, n: int, batch: int = 1, dtype=torch.complex64, max_candidates: int = 0):
+        """The fastest of the configurations fft_plan_create_tuned times for
+        this shape; returns (plan, result dict)."""
+        self = cls.__new__(cls)
+        self._h = ctypes.c_void_p()
+        self.n, self.batch = int(n), int(batch)
+        self.dtype_code = dtype_code(dtype)
+        self.torch_dtype = torch.complex64 if self.dtype_code == FFT_C64 else torch.complex128
+        res = TuneResult()
+        rc = lib().fft_plan_create_tuned(self.n, self.batch, self.dtype_code, int(max_candidates),
+                                         ctypes.byref(self._h), ctypes.byref(res))
+        _check(rc, "fft_plan_create_tuned(n=%d, batch=%d)" % (self.n, self.batch))
+        return self, res.as_dict()
 
     @classmethod
     def uneven(cls, lengths, dtype=torch.complex64, graph: bool = True) -> "Plan":

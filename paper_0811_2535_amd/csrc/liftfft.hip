@@ -24,6 +24,9 @@
 #include <string.h>
 
 #include <array>
+#include <cmath>
+#include <map>
+#include <mutex>
 #include <type_traits>
 #include <new>
 #include <utility>
@@ -471,6 +474,54 @@ __global__ void twiddle_table_kernel(typename Cx<Real>::T *out, int64_t count, i
     w.x = Real(c);
     w.y = Real(s);
     out[i] = w;
+}
+
+// Tuner helpers.  A deterministic input pattern in [-1, 1) (an integer
+// hash of the index), and per-block maxima of |a - b| and |b| for comparing
+// two outputs (finished on the host).
+template <typename Real>
+__global__ void fill_pattern_kernel(typename Cx<Real>::T *x, int64_t count) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    uint32_t h = uint32_t(i) * 2654435761u ^ uint32_t(i >> 32);
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    typename Cx<Real>::T v;
+    v.x = Real(int32_t(h & 0xffff) - 32768) / Real(32768);
+    v.y = Real(int32_t(h >> 16) - 32768) / Real(32768);
+    x[i] = v;
+}
+
+constexpr int CMP_THREADS = 256;
+
+template <typename Real>
+__global__ __launch_bounds__(CMP_THREADS) void compare_kernel(const typename Cx<Real>::T *a,
+                                                              const typename Cx<Real>::T *b, int64_t count,
+                                                              double *partial) {
+    __shared__ double sd[CMP_THREADS], sb[CMP_THREADS];
+    double md = 0, mb = 0;
+    for (int64_t i = int64_t(blockIdx.x) * CMP_THREADS + threadIdx.x; i < count;
+         i += int64_t(gridDim.x) * CMP_THREADS) {
+        const double dx = double(a[i].x) - double(b[i].x), dy = double(a[i].y) - double(b[i].y);
+        const double d = fmax(fabs(dx), fabs(dy)), m = fmax(fabs(double(b[i].x)), fabs(double(b[i].y)));
+        md = isnan(d) ? INFINITY : fmax(md, d);
+        mb = fmax(mb, m);
+    }
+    sd[threadIdx.x] = md;
+    sb[threadIdx.x] = mb;
+    __syncthreads();
+    for (int w = CMP_THREADS / 2; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) {
+            sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + w]);
+            sb[threadIdx.x] = fmax(sb[threadIdx.x], sb[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = sd[0];
+        partial[2 * blockIdx.x + 1] = sb[0];
+    }
 }
 
 using KernelFn = void (*)(PassArgs);
@@ -1472,6 +1523,224 @@ int fft_plan_read_timing(fft_plan *p, double ms_out[2], int64_t launches_out[2],
         p->launches[0] = p->launches[1] = 0;
     }
     return rc;
+}
+
+
+} // extern "C"
+
+namespace {
+
+// Options of the best configuration found so far per (n, batch, dtype,
+// device), so that a second tuned plan of the same shape is created directly.
+struct TuneKey {
+    int64_t n, batch;
+    int dtype, device;
+    bool operator<(const TuneKey &o) const {
+        return n != o.n ? n < o.n : batch != o.batch ? batch < o.batch : dtype != o.dtype ? dtype < o.dtype
+                                                                                           : device < o.device;
+    }
+};
+std::mutex tune_mutex;
+std::map<TuneKey, fft_tune_result> tune_cache;
+
+// Candidate configurations, most promising first: the default; the other
+// splits n = p*q near the square one and the single/two-pass threshold;
+// radix 2; then, for the default split, the kernel variants and tile widths.
+std::vector<fft_plan_opts> tune_candidates(int t, int dtype) {
+    std::vector<fft_plan_opts> c;
+    auto add = [&](int log2_p, int radix, int lpb, int lpb2, int flags, int vpt) {
+        fft_plan_opts o;
+        memset(&o, 0, sizeof(o));
+        o.log2_p = log2_p;
+        o.radix = radix;
+        o.lines_per_block = lpb;
+        o.lines_per_block2 = lpb2;
+        o.flags = flags;
+        o.values_per_thread = vpt;
+        c.push_back(o);
+    };
+    add(0, 0, 0, 0, 0, 0);
+    const int lq = (t + 1) / 2, lp = t - lq;
+    for (int d : {1, -1, 2}) { // splits p = 2^(lp + d); q = 2^(t - lp - d)
+        const int l2p = lp + d;
+        if (l2p >= 1 && l2p < t && l2p <= MAX_LOG2_LINE && t - l2p <= MAX_LOG2_LINE) add(l2p, 0, 0, 0, 0, 0);
+    }
+    if (t <= MAX_LOG2_LINE && lp >= 1) add(lp, 0, 0, 0, 0, 0); // two passes below the threshold
+    add(0, 2, 0, 0, 0, 0);
+    if (t > MAX_LOG2_LINE || t >= 2) {
+        const int variants[][2] = {{FFT_OPT_FULL_EXCHANGE, 16}, {FFT_OPT_SPLIT_EXCHANGE, 16},
+                                   {FFT_OPT_SPLIT_EXCHANGE, 32}, {0, 32},
+                                   {FFT_OPT_PERSISTENT, 16}, {FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_DENSE, 16}};
+        const int tiles[][2] = {{0, 0}, {2, 4}, {1, 4}, {4, 4}, {2, 8}, {4, 8}, {8, 8}, {2, 2}};
+        for (const auto &tl : tiles)
+            for (const auto &v : variants) {
+                if (dtype != FFT_C64 && (v[0] != FFT_OPT_FULL_EXCHANGE || v[1] != 16)) continue;
+                add(0, 0, tl[0], tl[1], v[0], v[1] == 16 && !(v[0] & (FFT_OPT_PERSISTENT | FFT_OPT_DENSE)) ? 0 : v[1]);
+            }
+    }
+    return c;
+}
+
+struct TuneBench {
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    void *x = nullptr, *y = nullptr, *ref = nullptr;
+    double *partial = nullptr;
+    int64_t count = 0;
+    int dtype = 0;
+    ~TuneBench() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (x) (void)hipFree(x);
+        if (y) (void)hipFree(y);
+        if (ref) (void)hipFree(ref);
+        if (partial) (void)hipFree(partial);
+        if (st) (void)hipStreamDestroy(st);
+    }
+};
+constexpr int CMP_BLOCKS = 1024;
+
+// Milliseconds per forward execute of `plan` (negative on failure).
+double tune_time(const fft_plan *plan, TuneBench &b) {
+    for (int w = 0; w < 2; ++w)
+        if (fft_execute(plan, b.x, b.y, -1, b.st) != FFT_OK) return -1;
+    if (hipEventRecord(b.e0, b.st) != hipSuccess || fft_execute(plan, b.x, b.y, -1, b.st) != FFT_OK ||
+        hipEventRecord(b.e1, b.st) != hipSuccess || hipEventSynchronize(b.e1) != hipSuccess)
+        return -1;
+    float one = 0;
+    if (hipEventElapsedTime(&one, b.e0, b.e1) != hipSuccess) return -1;
+    int reps = one > 0 ? int(2.0 / one) : 50; // about 2 ms of timed work
+    reps = reps < 3 ? 3 : reps > 50 ? 50 : reps;
+    if (hipEventRecord(b.e0, b.st) != hipSuccess) return -1;
+    for (int r = 0; r < reps; ++r)
+        if (fft_execute(plan, b.x, b.y, -1, b.st) != FFT_OK) return -1;
+    float ms = 0;
+    if (hipEventRecord(b.e1, b.st) != hipSuccess || hipEventSynchronize(b.e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, b.e0, b.e1) != hipSuccess)
+        return -1;
+    return double(ms) / reps;
+}
+
+// Largest |y - ref| relative to the largest |ref| (after tune_time left the
+// candidate's output in y).
+double tune_diff(TuneBench &b) {
+    if (b.dtype == FFT_C64)
+        hipLaunchKernelGGL(compare_kernel<float>, dim3(CMP_BLOCKS), dim3(CMP_THREADS), 0, b.st,
+                           static_cast<const float2 *>(b.y), static_cast<const float2 *>(b.ref), b.count, b.partial);
+    else
+        hipLaunchKernelGGL(compare_kernel<double>, dim3(CMP_BLOCKS), dim3(CMP_THREADS), 0, b.st,
+                           static_cast<const double2 *>(b.y), static_cast<const double2 *>(b.ref), b.count,
+                           b.partial);
+    std::vector<double> h(2 * CMP_BLOCKS);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(h.data(), b.partial, h.size() * sizeof(double), hipMemcpyDeviceToHost, b.st) != hipSuccess ||
+        hipStreamSynchronize(b.st) != hipSuccess)
+        return INFINITY;
+    double md = 0, mb = 0;
+    for (int i = 0; i < CMP_BLOCKS; ++i) {
+        md = md > h[2 * i] ? md : h[2 * i];
+        mb = mb > h[2 * i + 1] ? mb : h[2 * i + 1];
+    }
+    return mb > 0 ? md / mb : md;
+}
+
+} // namespace
+
+extern "C" {
+
+int fft_plan_create_tuned(int64_t n, int64_t batch, int dtype, int32_t max_candidates, fft_plan **plan_out,
+                          fft_tune_result *result) {
+    if (!plan_out) return FFT_E_NULL;
+    *plan_out = nullptr;
+    if (max_candidates < 0) return FFT_E_ARG;
+    // The default plan validates the arguments and is the reference output.
+    fft_plan *best = nullptr;
+    int rc = fft_plan_create(n, batch, dtype, &best);
+    if (rc != FFT_OK) return rc;
+    const TuneKey key{n, batch, dtype, best->device};
+    {
+        std::lock_guard<std::mutex> g(tune_mutex);
+        auto it = tune_cache.find(key);
+        if (it != tune_cache.end()) {
+            fft_plan *p = nullptr;
+            rc = fft_plan_create_ex(n, batch, dtype, &it->second.opts, &p);
+            if (rc == FFT_OK) {
+                fft_plan_destroy(best);
+                if (result) *result = it->second;
+                *plan_out = p;
+                return FFT_OK;
+            }
+        }
+    }
+    TuneBench b;
+    b.dtype = dtype;
+    b.count = n * batch;
+    const size_t bytes = size_t(b.count) * best->esize;
+    if (hipStreamCreateWithFlags(&b.st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&b.e0) != hipSuccess || hipEventCreate(&b.e1) != hipSuccess) {
+        (void)hipGetLastError();
+        fft_plan_destroy(best);
+        return FFT_E_HIP;
+    }
+    if (hipMalloc(&b.x, bytes) != hipSuccess || hipMalloc(&b.y, bytes) != hipSuccess ||
+        hipMalloc(&b.ref, bytes) != hipSuccess || hipMalloc(&b.partial, 2 * CMP_BLOCKS * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        fft_plan_destroy(best);
+        return FFT_E_OOM;
+    }
+    const int64_t fb = (b.count + 255) / 256;
+    if (dtype == FFT_C64)
+        hipLaunchKernelGGL(fill_pattern_kernel<float>, dim3(unsigned(fb)), dim3(256), 0, b.st,
+                           static_cast<float2 *>(b.x), b.count);
+    else
+        hipLaunchKernelGGL(fill_pattern_kernel<double>, dim3(unsigned(fb)), dim3(256), 0, b.st,
+                           static_cast<double2 *>(b.x), b.count);
+    if (hipGetLastError() != hipSuccess || fft_execute(best, b.x, b.ref, -1, b.st) != FFT_OK ||
+        hipStreamSynchronize(b.st) != hipSuccess) {
+        (void)hipGetLastError();
+        fft_plan_destroy(best);
+        return FFT_E_HIP;
+    }
+    double best_ms = tune_time(best, b);
+    if (best_ms < 0) {
+        fft_plan_destroy(best);
+        return FFT_E_HIP;
+    }
+    fft_tune_result res;
+    memset(&res, 0, sizeof(res));
+    res.ms_default = best_ms;
+    res.candidates = 1;
+    const double tol = dtype == FFT_C64 ? 1e-4 : 1e-10;
+    const int limit = max_candidates ? max_candidates : 48;
+    const std::vector<fft_plan_opts> cands = tune_candidates(ilog2_exact(n), dtype);
+    for (size_t i = 1; i < cands.size() && res.candidates < limit; ++i) {
+        fft_plan *p = nullptr;
+        if (fft_plan_create_ex(n, batch, dtype, &cands[i], &p) != FFT_OK) continue;
+        const double ms = tune_time(p, b);
+        ++res.candidates;
+        if (ms < 0 || !(tune_diff(b) <= tol)) { // a configuration that disagrees is never chosen
+            ++res.rejected;
+            fft_plan_destroy(p);
+            continue;
+        }
+        if (ms < best_ms) {
+            fft_plan_destroy(best);
+            best = p;
+            best_ms = ms;
+            res.opts = cands[i];
+        } else {
+            fft_plan_destroy(p);
+        }
+    }
+    (void)hipStreamSynchronize(b.st);
+    res.ms = best_ms;
+    {
+        std::lock_guard<std::mutex> g(tune_mutex);
+        tune_cache[key] = res;
+    }
+    if (result) *result = res;
+    *plan_out = best;
+    return FFT_OK;
 }
 
 } // extern "C"

@@ -128,3 +128,13 @@ def test_create_many_validation():
     for opts in (PlanOpts(0, 2, 0), PlanOpts(3, 0, 0), PlanOpts(0, 0, 4), PlanOpts(0, 0, 0, 2),
                  PlanOpts(0, 0, 0, 0, 1), PlanOpts(0, 0, 0, 0, 2), PlanOpts(0, 0, 0, 0, 0, 16)):
         assert L.fft_plan_create_many(arr(8, 16), 2, 0, ctypes.byref(opts), ctypes.byref(h)) == -9
+
+
+def test_create_tuned_validation():
+    from paper_0811_2535_amd.binding import TuneResult
+    L = _lib()
+    h = ctypes.c_void_p(123)
+    res = TuneResult()
+    assert L.fft_plan_create_tuned(1024, 1, 0, 0, None, ctypes.byref(res)) == -4
+    assert L.fft_plan_create_tuned(1024, 1, 0, -1, ctypes.byref(h), ctypes.byref(res)) == -9
+    assert h.value is None
