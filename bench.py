@@ -60,9 +60,9 @@ def load_traffic(kernel: str, launches_bytes: float):
 
 
 def _kernel_role(name: str) -> str | None:
-    if "pass_kernel<float, 4096, 16, 1>" in name:
+    if "pass_kernel<float, 4096, 16, 1," in name:
         return "pass1"
-    if "pass_kernel<float, 4096, 16, 2>" in name:
+    if "pass_kernel<float, 4096, 16, 2," in name:
         return "pass2"
     if "neg" in name:
         return "reference"
@@ -93,7 +93,7 @@ def summarize_counters(fetch_csv: str, write_csv: str, log2n: int, out_path: str
     fetch, nf = per_role(fetch_csv, "FETCH_SIZE")
     write, nw = per_role(write_csv, "WRITE_SIZE")
     f_fac, w_fac = known / fetch["reference"], known / write["reference"]
-    bargs = "--steps 2 --warmup 1 --sets 4 --copy-reps 3 --no-cpu-baseline"
+    bargs = "--steps 2 --warmup 1 --sets 4 --copy-reps 3 --no-cpu-baseline --no-extras"
     rec = {"source_hash": kernel_source_hash(), "log2n": log2n,
            "commands": [
                "timeout -s KILL 60 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch "
