@@ -190,6 +190,7 @@ const char *fft_strerror(int code);
  *   variant_pass1/2            kernel variant bits: 1 = 32 values per
  *                              thread, 2 = split exchange, 4 = persistent,
  *                              8 = dense (64-VGPR cap)
+ *   precision                  FFT_PREC_* set by fft_plan_set_precision
  *   length_classes, graph_launch  plans of uneven lengths: number of
  *                              distinct lengths, and whether executes replay
  *                              captured graphs (0 for single-length plans)
@@ -208,9 +209,27 @@ typedef struct fft_plan_info {
     int64_t scratch_bytes, table_bytes;
     int32_t variant_pass1, variant_pass2;
     int32_t length_classes, graph_launch;
+    int32_t precision, reserved0;
 } fft_plan_info;
 
 int fft_plan_get_info(const fft_plan *plan, fft_plan_info *info);
+
+/*
+ * Precision form of a plan (default FFT_PREC_FP32: every stage in the
+ * element type on the vector units).  FFT_PREC_F16X2 / FFT_PREC_BF16X2 run
+ * each radix-16 stage as a product with the 16 x 16 DFT matrix on the matrix
+ * cores: matrix and inputs split into high and low FP16 (BF16) parts, three
+ * partial products accumulated in FP32, FP16 inputs scaled per butterfly by
+ * a power of two.  This is a different arithmetic from the paper's radix-2
+ * butterflies (same transform, larger rounding error: about 1e-6 relative
+ * L2 for FP16 pairs, 1e-5 for BF16 pairs); tests state the measured error.
+ * Available for complex64 plans whose pass lines are 16, 256 or 4096 points
+ * (every stage radix 16) with radix 16, 16 values per thread and one tile
+ * per workgroup; otherwise FFT_E_UNSUPPORTED and the plan is unchanged.
+ * FFT_E_ARG for an unknown mode.  Takes effect for later executes.
+ */
+enum { FFT_PREC_FP32 = 0, FFT_PREC_F16X2 = 1, FFT_PREC_BF16X2 = 2 };
+int fft_plan_set_precision(fft_plan *plan, int mode);
 
 /*
  * Per-kernel timing, for benchmarks.  While enabled, fft_execute records a
@@ -252,7 +271,7 @@ int fft_plan_create_tuned(int64_t n, int64_t batch, int dtype, int32_t max_candi
                           fft_tune_result *result);
 
 /* ABI version of this header (major*100 + minor). */
-#define LIFTFFT_ABI_VERSION 103
+#define LIFTFFT_ABI_VERSION 104
 int fft_abi_version(void);
 
 #ifdef __cplusplus

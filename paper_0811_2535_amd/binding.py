@@ -28,7 +28,7 @@ STATUS = {
 EXPORTED = [
     "fft_plan_create", "fft_plan_create_ex", "fft_execute", "fft_plan_destroy",
     "fft_strerror", "fft_plan_get_info", "fft_plan_set_timing", "fft_plan_read_timing",
-    "fft_abi_version", "fft_plan_create_many", "fft_plan_create_tuned",
+    "fft_abi_version", "fft_plan_create_many", "fft_plan_create_tuned", "fft_plan_set_precision",
 ]
 
 
@@ -83,7 +83,8 @@ class PlanInfo(ctypes.Structure):
                 ("lds_bytes_pass1", ctypes.c_int64), ("lds_bytes_pass2", ctypes.c_int64),
                 ("scratch_bytes", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
                 ("variant_pass1", ctypes.c_int32), ("variant_pass2", ctypes.c_int32),
-                ("length_classes", ctypes.c_int32), ("graph_launch", ctypes.c_int32)]
+                ("length_classes", ctypes.c_int32), ("graph_launch", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -119,10 +120,11 @@ def lib():
             L.fft_strerror.restype = ctypes.c_char_p
             L.fft_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
             L.fft_plan_set_timing.argtypes = [vp, i32]
+            L.fft_plan_set_precision.argtypes = [vp, i32]
             L.fft_plan_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double * 2),
                                                ctypes.POINTER(ctypes.c_int64 * 2), i32]
             for name in ("fft_plan_create", "fft_plan_create_ex", "fft_plan_create_many",
-                         "fft_plan_create_tuned", "fft_execute",
+                         "fft_plan_create_tuned", "fft_plan_set_precision", "fft_execute",
                          "fft_plan_destroy", "fft_plan_get_info", "fft_plan_set_timing",
                          "fft_plan_read_timing", "fft_abi_version"):
                 getattr(L, name).restype = i32
@@ -237,6 +239,11 @@ class Plan:
         if stream is None:
             stream = torch.cuda.current_stream(x.device)
         self.execute_ptr(x.data_ptr(), out.data_ptr(), sign, stream.cuda_stream)
+
+    def set_precision(self, mode) -> None:
+        """'fp32' (default), 'f16x2' or 'bf16x2' (radix-16 stages on the matrix cores)."""
+        code = {"fp32": 0, "f16x2": 1, "bf16x2": 2}.get(mode, mode)
+        _check(lib().fft_plan_set_precision(self.handle, int(code)), "fft_plan_set_precision(%r)" % (mode,))
 
     def set_timing(self, enable: bool) -> None:
         _check(lib().fft_plan_set_timing(self.handle, int(bool(enable))), "fft_plan_set_timing")

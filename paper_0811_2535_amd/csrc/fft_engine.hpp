@@ -224,14 +224,21 @@ inline int exchange_pitch(int N, int T, int TPL, int esize, bool lines_first) {
 // lines, the stage twiddle tables (16-byte aligned) and, in pass 1, two
 // buffers of the inter-pass weight table of T x (E+1) entries (alternate
 // tiles of a persistent workgroup use alternate buffers).
-__host__ __device__ constexpr int64_t lds_tile_bytes(int N, int RMAX, int T, int pitch, int lsize) {
-    return uses_tile(N, RMAX) ? ((int64_t(T) * pitch * lsize + 15) & ~int64_t(15)) : 0;
+// `force` keeps the exchange tile for single-stage schedules (the
+// matrix-core stages always pass through LDS).
+__host__ __device__ constexpr int64_t lds_tile_bytes(int N, int RMAX, int T, int pitch, int lsize,
+                                                     bool force = false) {
+    return (uses_tile(N, RMAX) || force) ? ((int64_t(T) * pitch * lsize + 15) & ~int64_t(15)) : 0;
 }
-__host__ __device__ constexpr int64_t lds_ep_offset(int N, int RMAX, int T, int pitch, int lsize, int csize) {
-    return lds_tile_bytes(N, RMAX, T, pitch, lsize) + (uses_tile(N, RMAX) ? int64_t(tw_total(N, RMAX)) * csize : 0);
+__host__ __device__ constexpr int64_t lds_ep_offset(int N, int RMAX, int T, int pitch, int lsize, int csize,
+                                                    bool force = false) {
+    return lds_tile_bytes(N, RMAX, T, pitch, lsize, force) +
+           (uses_tile(N, RMAX) ? int64_t(tw_total(N, RMAX)) * csize : 0);
 }
-inline int64_t lds_bytes(int N, int RMAX, int T, int E, int pitch, int lsize, int csize, bool epilogue) {
-    return lds_ep_offset(N, RMAX, T, pitch, lsize, csize) + (epilogue ? 2 * int64_t(T) * (E + 1) * csize : 0);
+inline int64_t lds_bytes(int N, int RMAX, int T, int E, int pitch, int lsize, int csize, bool epilogue,
+                         bool force = false) {
+    return lds_ep_offset(N, RMAX, T, pitch, lsize, csize, force) +
+           (epilogue ? 2 * int64_t(T) * (E + 1) * csize : 0);
 }
 
 template <int N> __device__ __forceinline__ constexpr int lpad(int e) { return e + (e >> 4); }
@@ -379,6 +386,165 @@ __device__ __forceinline__ void run_stages(C *v, void *line_base, const C *twl, 
         }
         run_stages<C, N, RMAX, E, SPLIT, STG + 1>(v, line_base, twl, j);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Precision forms on the matrix cores.  A radix-16 stage is, per group of 16
+// butterflies, the product of the 16 x 16 DFT matrix with a 16 x 16 block of
+// inputs.  With complex numbers split into real and imaginary rows this is
+// two real products Yr = [Re F | -Im F] [Xr; Xi], Yi = [Im F | Re F] [Xr; Xi]
+// of a 16 x 32 matrix and a 32 x 16 block -- one v_mfma_f32_16x16x32 each.
+// FP16 / BF16 operands keep 11 / 8 significant bits, so both the DFT matrix
+// and the inputs are split into a high and a low part, x = hi + lo, and the
+// product is accumulated in FP32 as A_hi B_hi + A_hi B_lo + A_lo B_hi (the
+// lo*lo term is below the FP32 rounding of the result).  FP16 inputs are
+// scaled per butterfly by a power of two (exact) so that the largest of its
+// 32 real parts lies in [2^14, 2^15): full use of the FP16 range, no
+// overflow (|hi| < 65504); BF16 has the FP32 exponent range and is not
+// scaled.
+//
+// Operand layout of v_mfma_f32_16x16x32 (checked on the device): lane l,
+// element i holds A[l % 16][8(l/16) + i] and B[8(l/16) + i][l % 16]; the FP32
+// result D[4(l/16) + i][l % 16] is element i of lane l.  Row k of the input
+// block is the real part (k < 16) or the imaginary part (k >= 16) of input
+// r = k % 16 of butterfly n.
+enum { PREC_FP32 = 0, PREC_F16X2 = 1, PREC_BF16X2 = 2 };
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int PREC> struct MfmaOps;
+template <> struct MfmaOps<PREC_F16X2> {
+    using V = half8;
+    using S = _Float16;
+    static constexpr bool SCALE = true;
+    __device__ static __forceinline__ f32x4 mma(V a, V b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct MfmaOps<PREC_BF16X2> {
+    using V = bf16x8;
+    using S = __bf16;
+    static constexpr bool SCALE = false;
+    __device__ static __forceinline__ f32x4 mma(V a, V b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+// x = hi + lo in the operand type (lo rounds the remainder once more).
+template <int PREC>
+__device__ __forceinline__ void split_hilo(const float *x, typename MfmaOps<PREC>::V &hi, typename MfmaOps<PREC>::V &lo) {
+    using S = typename MfmaOps<PREC>::S;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const S h = S(x[i]);
+        hi[i] = h;
+        lo[i] = S(x[i] - float(h));
+    }
+}
+
+// This lane's share of the two DFT-matrix operands (forward sign), split
+// into hi and lo parts: row m = l % 16, columns k = 8(l/16) + i.
+template <int PREC> struct DftOperands {
+    typename MfmaOps<PREC>::V rh, rl, ih, il;
+    __device__ __forceinline__ explicit DftOperands(int lane) {
+        float ar[8], ai[8];
+        const int m = lane & 15;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = 8 * (lane >> 4) + i, r = k & 15, e = (m * r) & 15;
+            double sn, cs;
+            sincospi(double(e) / 8.0, &sn, &cs); // angle 2*pi*e/16
+            // F[m][r] = cos - i sin;  Yr = sum cos Xr + sin Xi;  Yi = sum -sin Xr + cos Xi
+            ar[i] = float(k < 16 ? cs : sn);
+            ai[i] = float(k < 16 ? -sn : cs);
+        }
+        split_hilo<PREC>(ar, rh, rl);
+        split_hilo<PREC>(ai, ih, il);
+    }
+};
+
+// The whole radix-16 stage schedule of a tile on the matrix cores.  N is a
+// power of 16 (every stage radix 16); each wave owns 64 butterflies per stage
+// (four groups of 16), so T * N/16 must be a multiple of 64.
+//   v      on entry the thread's 16 inputs of stage 0 (slot r = element
+//          j + r*N/16 of line c), on exit its 16 outputs in the same layout
+//   tile   the LDS tile (complex elements, line pitch `pitch`)
+//   twl    the stage twiddle tables (as for run_stages)
+// Stage s writes output k of butterfly b to (b/NS)*NS*16 + b%NS + k*NS and
+// applies there the twiddle the next stage would apply to that element.
+template <int PREC, int N>
+__device__ __forceinline__ void mfma_stages(float2 *v, float2 *tile, int pitch, const float2 *twl, int c, int j,
+                                            int tid, const DftOperands<PREC> &F) {
+    using Ops = MfmaOps<PREC>;
+    constexpr int TPL = N / 16, NST = sched_nstages(N, 16);
+    static_assert(N >= 16 && ilog2c(N) % 4 == 0, "all stages radix 16");
+    const int lane = tid & 63, wave = tid >> 6;
+    const int rb = 8 * ((lane >> 4) & 1), comp = lane >> 5, kb = 4 * (lane >> 4);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) tile[c * pitch + lpad<N>(j + r * TPL)] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NST; ++s) {
+        const int NS = 1 << (4 * s);
+        float x[4][8];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int bf = 64 * wave + 16 * g + (lane & 15), cc = bf / TPL, b = bf % TPL;
+            const float *ln = reinterpret_cast<const float *>(tile + cc * pitch);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) x[g][i] = ln[2 * lpad<N>(b + (rb + i) * TPL) + comp];
+        }
+        __syncthreads(); // every read of this stage precedes its writes
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            float scale = 1.f, unscale = 1.f;
+            if constexpr (Ops::SCALE) {
+                float mx = 0.f;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) mx = fmaxf(mx, fabsf(x[g][i]));
+                mx = fmaxf(mx, __shfl_xor(mx, 16));
+                mx = fmaxf(mx, __shfl_xor(mx, 32));
+                if (mx > 0.f) {
+                    int e;
+                    (void)frexpf(mx, &e); // mx in [2^(e-1), 2^e)
+                    scale = ldexpf(1.f, 15 - e);
+                    unscale = ldexpf(1.f, e - 15);
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) x[g][i] *= scale;
+            }
+            typename Ops::V bh, bl;
+            split_hilo<PREC>(x[g], bh, bl);
+            const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+            f32x4 yr = Ops::mma(F.rh, bh, z);
+            yr = Ops::mma(F.rh, bl, yr);
+            yr = Ops::mma(F.rl, bh, yr);
+            f32x4 yi = Ops::mma(F.ih, bh, z);
+            yi = Ops::mma(F.ih, bl, yi);
+            yi = Ops::mma(F.il, bh, yi);
+            const int bf = 64 * wave + 16 * g + (lane & 15), cc = bf / TPL, b = bf % TPL;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = kb + i, p = (b / NS) * NS * 16 + (b % NS) + k * NS;
+                float2 o = mk<float2>(yr[i] * unscale, yi[i] * unscale);
+                if (s + 1 < NST) {
+                    // next stage's twiddle of element p: input r2 = p / TPL of
+                    // butterfly b2 = p % TPL, exponent r2 * (b2 mod 16^(s+1))
+                    const int NS2 = NS * 16, r2 = p / TPL, k2 = (p % TPL) & (NS2 - 1);
+                    const int off = tw_stage_off(N, 16, s + 1);
+                    float2 w = twl[off + (k2 & 15) * 17 + r2];
+                    if (NS2 > 16) w = cmul(w, twl[off + (16 + (k2 >> 4)) * 17 + r2]);
+                    o = cmulc(o, w);
+                }
+                tile[cc * pitch + lpad<N>(p)] = o;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = tile[c * pitch + lpad<N>(j + r * TPL)];
 }
 
 } // namespace liftfft

@@ -102,7 +102,12 @@ template <bool DENSE> constexpr int min_waves() { return DENSE ? 8 : 1; }
 // element and the single-pass descriptor covers the whole packed buffer).
 //   EMAX   complex values per thread (16 or 32)
 //   SPLIT  exchange real and imaginary parts in turn (half the LDS)
-template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT> struct Tile {
+//   PREC   PREC_FP32: stages in FP32 on the vector units; PREC_F16X2 /
+//          PREC_BF16X2: radix-16 stages on the matrix cores (mfma_stages)
+struct NoOperands {
+    __device__ __forceinline__ explicit NoOperands(int) {}
+};
+template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PREC = PREC_FP32> struct Tile {
     using C = typename Cx<Real>::T;
     using L = typename std::conditional<SPLIT, Real, C>::type; // exchange element
     static constexpr uint32_t ES = sizeof(C);
@@ -114,13 +119,15 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT> struct
     const PassArgs &a;
     int log2T, T, tid, nthr, c, j;
     L *line;
+    C *tile;
+    typename std::conditional<PREC == PREC_FP32, NoOperands, DftOperands<PREC>>::type F;
     C *twl, *ep_base;
     Real sin_, sout;
     const C *__restrict__ in;
     C *__restrict__ out;
     int64_t pmask, qmask;
 
-    __device__ __forceinline__ Tile(const PassArgs &args, unsigned char *smem) : a(args) {
+    __device__ __forceinline__ Tile(const PassArgs &args, unsigned char *smem) : a(args), F(int(threadIdx.x & 63)) {
         log2T = a.log2T;
         T = 1 << log2T;
         tid = threadIdx.x;
@@ -133,8 +140,10 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT> struct
             c = tid / TPL;
         }
         line = reinterpret_cast<L *>(smem) + c * a.pitch;
-        twl = reinterpret_cast<C *>(smem + lds_tile_bytes(N, RMAX, T, a.pitch, sizeof(L)));
-        ep_base = reinterpret_cast<C *>(smem + lds_ep_offset(N, RMAX, T, a.pitch, sizeof(L), sizeof(C)));
+        tile = reinterpret_cast<C *>(smem);
+        constexpr bool force = PREC != PREC_FP32;
+        twl = reinterpret_cast<C *>(smem + lds_tile_bytes(N, RMAX, T, a.pitch, sizeof(L), force));
+        ep_base = reinterpret_cast<C *>(smem + lds_ep_offset(N, RMAX, T, a.pitch, sizeof(L), sizeof(C), force));
         sin_ = a.conj_in ? Real(-1) : Real(1);
         sout = a.conj_out ? Real(-1) : Real(1);
         in = static_cast<const C *>(a.in);
@@ -242,7 +251,8 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT> struct
         const bool active = line0 + c < a.lines;
         if constexpr (KIND == K_PASS1 && !TILE) __syncthreads();
 
-        run_stages<C, N, RMAX, E, SPLIT>(v, line, twl, j);
+        if constexpr (PREC == PREC_FP32) run_stages<C, N, RMAX, E, SPLIT>(v, line, twl, j);
+        else mfma_stages<PREC, N>(v, tile, a.pitch, twl, c, j, tid, F);
 
         if (!active) return;
         if constexpr (KIND == K_SINGLE) {
@@ -292,10 +302,11 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT> struct
 // one is transformed.
 //   DENSE  registers capped at 64 VGPRs so that two 1024-thread
 //          workgroups share a CU
-template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, bool PERSIST, bool DENSE>
+template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, bool PERSIST, bool DENSE,
+          int PREC = PREC_FP32>
 __global__ __launch_bounds__((max_threads<Real, EMAX, PERSIST>()), (min_waves<DENSE>())) void pass_kernel(
     PassArgs a) {
-    using W = Tile<Real, N, RMAX, KIND, EMAX, SPLIT>;
+    using W = Tile<Real, N, RMAX, KIND, EMAX, SPLIT, PREC>;
     using C = typename W::C;
     constexpr int E = W::E, TPL = W::TPL, RL = W::RL;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -532,8 +543,11 @@ struct Variant {
     bool split = false;   // real/imaginary exchange in turn
     bool persist = false; // persistent workgroups with next-tile prefetch
     bool dense = false;   // 64-VGPR cap (two 1024-thread workgroups per CU)
-    bool is_default() const { return emax == 16 && !split && !persist && !dense; }
-    int code() const { return (emax == 32 ? 1 : 0) | (split ? 2 : 0) | (persist ? 4 : 0) | (dense ? 8 : 0); }
+    int prec = 0;         // PREC_*: radix-16 stages on the matrix cores when nonzero
+    bool is_default() const { return emax == 16 && !split && !persist && !dense && !prec; }
+    int code() const {
+        return (emax == 32 ? 1 : 0) | (split ? 2 : 0) | (persist ? 4 : 0) | (dense ? 8 : 0) | (prec << 4);
+    }
 };
 
 template <typename Real, int KIND, int RMAX, int VAR, int LMIN, int L> constexpr KernelFn kernel_entry() {
@@ -586,7 +600,28 @@ template <int KIND> KernelFn pick_variant(int log2N, const Variant &v) {
     }
 }
 
+// Matrix-core kernels: complex64, lines of 16, 256 or 4096 points (every
+// stage radix 16), 16 values per thread, complex exchange, one tile each.
+template <int KIND, int PREC> KernelFn pick_mfma(int log2N) {
+    switch (log2N) {
+    case 4: return &pass_kernel<float, 16, 16, KIND, 16, false, false, false, PREC>;
+    case 8: return &pass_kernel<float, 256, 16, KIND, 16, false, false, false, PREC>;
+    case 12: return &pass_kernel<float, 4096, 16, KIND, 16, false, false, false, PREC>;
+    default: return nullptr;
+    }
+}
+template <int PREC> KernelFn pick_mfma_kind(int kind, int log2N) {
+    return kind == K_SINGLE ? pick_mfma<K_SINGLE, PREC>(log2N)
+           : kind == K_PASS1 ? pick_mfma<K_PASS1, PREC>(log2N)
+                             : pick_mfma<K_PASS2, PREC>(log2N);
+}
+
 KernelFn pick_kernel(int dtype, int kind, int log2N, int rmax, const Variant &v) {
+    if (v.prec) {
+        if (dtype != FFT_C64 || rmax != 16 || v.emax != 16 || v.split || v.persist || v.dense) return nullptr;
+        return v.prec == PREC_F16X2 ? pick_mfma_kind<PREC_F16X2>(kind, log2N)
+                                    : pick_mfma_kind<PREC_BF16X2>(kind, log2N);
+    }
     if (v.is_default())
         return dtype == FFT_C64 ? pick_default<float>(kind, log2N, rmax)
                                 : pick_default<double>(kind, log2N, rmax);
@@ -610,6 +645,7 @@ int ilog2_exact(int64_t v) {
 struct Launch {
     KernelFn fn = nullptr;
     Variant var;
+    int kind = 0, rmax = 16;
     int log2N = 0, log2T = 0;
     int64_t lines = 0, ntiles = 0, grid = 0;
     int threads = 0;
@@ -631,6 +667,9 @@ struct fft_plan {
     size_t table_bytes = 0;
     const void *tw1 = nullptr, *tw2 = nullptr, *tw_hi = nullptr, *tw_lo = nullptr;
     Launch k1, k2;
+    Variant base1, base2; // the variants chosen at creation (precision FP32)
+    bool no_remap = false;
+    int precision = 0;
     int64_t total = 0; // elements in the input (and output) buffer
     // Packed batch of uneven lengths: two persistent launches over classes
     // of equal length, replayed as one captured graph per (in, out, sign).
@@ -681,7 +720,7 @@ TileShape tile_shape(int log2N, int rmax, size_t esize, int log2T, const Variant
     const int lsize = int(v.split ? esize / 2 : esize);
     TileShape ts;
     ts.pitch = exchange_pitch(N, T, N / E, lsize, kind != K_SINGLE);
-    ts.lds = lds_bytes(N, rmax, T, E, ts.pitch, lsize, int(esize), kind == K_PASS1);
+    ts.lds = lds_bytes(N, rmax, T, E, ts.pitch, lsize, int(esize), kind == K_PASS1, v.prec != 0);
     return ts;
 }
 
@@ -723,6 +762,9 @@ bool fill_launch(Launch &L, int dtype, int kind, int log2N, int rmax, int log2T,
     L.lines = lines;
     L.threads = (N / vals_per_thread(N, v.emax)) << log2T;
     if (L.threads > thread_cap(esize, v)) return false;
+    if (v.prec && L.threads % 64) return false; // waves own 64 butterflies per stage
+    L.kind = kind;
+    L.rmax = rmax;
     L.ntiles = (lines + (int64_t(1) << log2T) - 1) >> log2T;
     const TileShape ts = tile_shape(log2N, rmax, esize, log2T, v, kind);
     if (ts.lds > LDS_BUDGET) return false;
@@ -1048,6 +1090,9 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
         }
     }
     if (o.flags & FFT_OPT_NO_XCD_REMAP) p->k1.remap = p->k2.remap = false;
+    p->no_remap = (o.flags & FFT_OPT_NO_XCD_REMAP) != 0;
+    p->base1 = p->k1.var;
+    p->base2 = p->k2.var;
     if (!p->k1.fn || (p->passes == 2 && !p->k2.fn)) {
         free_plan(p);
         return FFT_E_UNSUPPORTED;
@@ -1475,6 +1520,7 @@ int fft_plan_get_info(const fft_plan *p, fft_plan_info *info) {
     info->table_bytes = int64_t(p->table_bytes);
     info->variant_pass1 = p->k1.var.code();
     info->variant_pass2 = p->passes == 2 ? p->k2.var.code() : 0;
+    info->precision = p->precision;
     if (p->ragged) {
         info->lines_per_block_pass1 = info->lines_per_block_pass2 = 0;
         info->grid_pass1 = int32_t(p->ra.grid);
@@ -1487,6 +1533,28 @@ int fft_plan_get_info(const fft_plan *p, fft_plan_info *info) {
         info->length_classes = p->length_classes;
         info->graph_launch = p->use_graph ? 1 : 0;
     }
+    return FFT_OK;
+}
+
+int fft_plan_set_precision(fft_plan *p, int mode) {
+    if (!p) return FFT_E_NULL;
+    if (mode != FFT_PREC_FP32 && mode != FFT_PREC_F16X2 && mode != FFT_PREC_BF16X2) return FFT_E_ARG;
+    if (p->ragged) return mode == FFT_PREC_FP32 ? FFT_OK : FFT_E_UNSUPPORTED;
+    Launch n1 = p->k1, n2 = p->k2;
+    auto redo = [&](Launch &L, const Variant &base) {
+        Variant v = base;
+        if (mode != FFT_PREC_FP32) {
+            v.split = false; // the matrix-core stages exchange complex elements
+            v.prec = mode;
+        }
+        if (!fill_launch(L, p->dtype, L.kind, L.log2N, L.rmax, L.log2T, L.lines, v, p->device)) return false;
+        if (p->no_remap) L.remap = false;
+        return true;
+    };
+    if (!redo(n1, p->base1) || (p->passes == 2 && !redo(n2, p->base2))) return FFT_E_UNSUPPORTED;
+    p->k1 = n1;
+    p->k2 = n2;
+    p->precision = mode;
     return FFT_OK;
 }
 
