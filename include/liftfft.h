@@ -108,6 +108,13 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out);
  *                     thread, one tile per workgroup only).
  *   values_per_thread complex values each thread holds in the pass kernels:
  *                     0 (default), 16 or 32.
+ *   values_per_thread2  the same for pass 2 only (0 = as values_per_thread).
+ *   scratch_width     W, the width of the slabs S[j1/W][k2][j1%W] of the
+ *                     scratch array between the passes (0 = pass 1's tile
+ *                     width; a power of two at most the threads of one pass-2
+ *                     line, else FFT_E_UNSUPPORTED).  Wider slabs give pass 2
+ *                     longer contiguous reads; narrower ones pass 1 longer
+ *                     contiguous writes.
  * Kernel variants other than the defaults exist for complex64 two-pass
  * plans with radix 16 and pass lines of 2^10..2^12; asking for one elsewhere
  * returns FFT_E_UNSUPPORTED.  Contradictory flags return FFT_E_ARG.
@@ -127,7 +134,8 @@ typedef struct fft_plan_opts {
     int32_t lines_per_block2;
     int32_t flags;
     int32_t values_per_thread;
-    int32_t reserved[2];
+    int32_t values_per_thread2;
+    int32_t scratch_width;
 } fft_plan_opts;
 
 /* As fft_plan_create with explicit options (opts may be NULL). */
@@ -271,7 +279,7 @@ int fft_plan_create_tuned(int64_t n, int64_t batch, int dtype, int32_t max_candi
                           fft_tune_result *result);
 
 /* ABI version of this header (major*100 + minor). */
-#define LIFTFFT_ABI_VERSION 104
+#define LIFTFFT_ABI_VERSION 105
 int fft_abi_version(void);
 
 #ifdef __cplusplus

@@ -56,7 +56,7 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("log2_p", ctypes.c_int32), ("radix", ctypes.c_int32),
                 ("lines_per_block", ctypes.c_int32), ("lines_per_block2", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("values_per_thread", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("values_per_thread2", ctypes.c_int32), ("scratch_width", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):
@@ -67,7 +67,8 @@ class TuneResult(ctypes.Structure):
         o = self.opts
         return {"opts": {"log2_p": o.log2_p, "radix": o.radix, "lines_per_block": o.lines_per_block,
                          "lines_per_block2": o.lines_per_block2, "flags": o.flags,
-                         "values_per_thread": o.values_per_thread},
+                         "values_per_thread": o.values_per_thread,
+                         "values_per_thread2": o.values_per_thread2, "scratch_width": o.scratch_width},
                 "ms": self.ms, "ms_default": self.ms_default, "candidates": self.candidates,
                 "rejected": self.rejected}
 
@@ -198,13 +199,14 @@ class Plan:
 
     def __init__(self, n: int, batch: int = 1, dtype=torch.complex64, log2_p: int = 0,
                  radix: int = 0, lines_per_block: int = 0, lines_per_block2: int = 0,
-                 flags: int = 0, values_per_thread: int = 0):
+                 flags: int = 0, values_per_thread: int = 0, values_per_thread2: int = 0,
+                 scratch_width: int = 0):
         self._h = ctypes.c_void_p()
         self.n, self.batch = int(n), int(batch)
         self.dtype_code = dtype_code(dtype)
         self.torch_dtype = torch.complex64 if self.dtype_code == FFT_C64 else torch.complex128
         opts = PlanOpts(int(log2_p), int(radix), int(lines_per_block), int(lines_per_block2),
-                        int(flags), int(values_per_thread))
+                        int(flags), int(values_per_thread), int(values_per_thread2), int(scratch_width))
         rc = lib().fft_plan_create_ex(self.n, self.batch, self.dtype_code, ctypes.byref(opts),
                                       ctypes.byref(self._h))
         _check(rc, "fft_plan_create_ex(n=%d, batch=%d)" % (self.n, self.batch))

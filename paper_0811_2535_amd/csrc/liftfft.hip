@@ -263,14 +263,20 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
             for (int s = 0; s < E; ++s)
                 buf_store(scale_im(v[s], sout), dst, lane, uint32_t(slot_off<N, E, RL>(s)) * ES);
         } else if constexpr (KIND == K_PASS1) {
-            // The tile's slabs of the scratch array S[j1/W][k2][j1%W]; the
-            // scratch width W = 2^log2T1 divides T (W = T in single-length
-            // plans).
+            // Slabs of the scratch array S[j1/W][k2][j1%W], W = 2^log2T1: the
+            // tile spans T/W whole slabs (W <= T) or T columns of one slab.
             const int64_t b = line0 >> a.log2p, j10 = line0 & pmask;
             const int lW = a.log2T1;
-            const rsrc_t dst = make_rsrc(out + base(b) + (j10 << a.log2q), uint32_t(T << a.log2q) * ES);
-            const uint32_t lane = ((uint32_t(c >> lW) << (a.log2q + lW)) + (uint32_t(j) << lW) +
-                                   uint32_t(c & ((1 << lW) - 1))) * ES;
+            rsrc_t dst;
+            uint32_t lane;
+            if (lW <= log2T) {
+                dst = make_rsrc(out + base(b) + (j10 << a.log2q), uint32_t(T << a.log2q) * ES);
+                lane = ((uint32_t(c >> lW) << (a.log2q + lW)) + (uint32_t(j) << lW) + uint32_t(c & ((1 << lW) - 1))) *
+                       ES;
+            } else {
+                dst = make_rsrc(out + base(b) + ((j10 >> lW) << (a.log2q + lW)), uint32_t(1u << (a.log2q + lW)) * ES);
+                lane = (uint32_t(j10 & ((1 << lW) - 1)) + uint32_t(c) + (uint32_t(j) << lW)) * ES;
+            }
             const C *P = ep + c * (E + 1);
 #pragma unroll
             for (int s = 0; s < E; ++s)
@@ -668,6 +674,7 @@ struct fft_plan {
     const void *tw1 = nullptr, *tw2 = nullptr, *tw_hi = nullptr, *tw_lo = nullptr;
     Launch k1, k2;
     Variant base1, base2; // the variants chosen at creation (precision FP32)
+    int log2W = 0;        // scratch slab width (two-pass plans)
     bool no_remap = false;
     int precision = 0;
     int64_t total = 0; // elements in the input (and output) buffer
@@ -1005,8 +1012,6 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
     fft_plan_opts o;
     memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
-    for (int r : o.reserved)
-        if (r) return FFT_E_ARG;
     int radix = o.radix ? o.radix : 16;
     if (radix != 2 && radix != 16) {
         if (radix == 4 || radix == 8) return FFT_E_UNSUPPORTED;
@@ -1022,13 +1027,18 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
     if ((o.flags & FFT_OPT_PERSISTENT) && (o.flags & FFT_OPT_ONE_TILE)) return FFT_E_ARG;
     if (o.values_per_thread != 0 && o.values_per_thread != 16 && o.values_per_thread != 32)
         return FFT_E_ARG;
+    if (o.values_per_thread2 != 0 && o.values_per_thread2 != 16 && o.values_per_thread2 != 32)
+        return FFT_E_ARG;
+    if (o.scratch_width < 0 || (o.scratch_width & (o.scratch_width - 1))) return FFT_E_ARG;
     // Pass-kernel variant: the defaults unless the options ask for another.
     Variant var;
     if (o.values_per_thread) var.emax = o.values_per_thread;
     if (o.flags & FFT_OPT_SPLIT_EXCHANGE) var.split = true;
     if (o.flags & FFT_OPT_PERSISTENT) var.persist = true;
     if (o.flags & FFT_OPT_DENSE) var.dense = true;
-    const bool forced = !var.is_default();
+    Variant var2 = var;
+    if (o.values_per_thread2) var2.emax = o.values_per_thread2;
+    const bool forced = !var.is_default() || !var2.is_default();
 
     fft_plan *p = new (std::nothrow) fft_plan;
     if (!p) return FFT_E_OOM;
@@ -1072,22 +1082,29 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
         // Default variant per pass: complex64 radix-16 lines of 2^10..2^12 use
         // the split exchange (measured faster at n = 2^24: the halved tile
         // lets more tiles share a CU; see the design notes).
-        auto pass_variant = [&](int log2N) {
-            Variant v = var;
+        auto pass_variant = [&](int log2N, const Variant &base) {
+            Variant v = base;
             if (!forced && !(o.flags & FFT_OPT_FULL_EXCHANGE) && dtype == FFT_C64 && radix == 16 &&
                 log2N >= VARIANT_LMIN)
                 v.split = true;
             return v;
         };
-        const Variant var1 = pass_variant(p->log2q), var2 = pass_variant(p->log2p);
-        const int tpl2 = int(P / vals_per_thread(int(P), var2.emax));
-        if (!plan_pass(p->k1, dtype, K_PASS1, p->log2q, radix, P, P * batch, o.lines_per_block, tpl2, var1,
-                       p->device) ||
-            !plan_pass(p->k2, dtype, K_PASS2, p->log2p, radix, Q, Q * batch, o.lines_per_block2, 0, var2,
+        const Variant v1 = pass_variant(p->log2q, var), v2 = pass_variant(p->log2p, var2);
+        const int tpl2 = int(P / vals_per_thread(int(P), v2.emax));
+        // Scratch slab width W: pass 1's tile width unless given; pass 2
+        // reads W-wide slabs with a separable offset, so W | TPL2.
+        if (o.scratch_width > tpl2) {
+            free_plan(p);
+            return FFT_E_UNSUPPORTED;
+        }
+        if (!plan_pass(p->k1, dtype, K_PASS1, p->log2q, radix, P, P * batch, o.lines_per_block,
+                       o.scratch_width ? 0 : tpl2, v1, p->device) ||
+            !plan_pass(p->k2, dtype, K_PASS2, p->log2p, radix, Q, Q * batch, o.lines_per_block2, 0, v2,
                        p->device)) {
             free_plan(p);
             return FFT_E_UNSUPPORTED;
         }
+        p->log2W = o.scratch_width ? ilog2_exact(o.scratch_width) : p->k1.log2T;
     }
     if (o.flags & FFT_OPT_NO_XCD_REMAP) p->k1.remap = p->k2.remap = false;
     p->no_remap = (o.flags & FFT_OPT_NO_XCD_REMAP) != 0;
@@ -1157,7 +1174,7 @@ int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const
     memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
     if (o.log2_p || (o.radix && o.radix != 16) || o.lines_per_block || o.lines_per_block2 ||
-        o.values_per_thread || o.reserved[0] || o.reserved[1] || (o.flags & ~int32_t(FFT_OPT_NO_GRAPH)))
+        o.values_per_thread || o.values_per_thread2 || o.scratch_width || (o.flags & ~int32_t(FFT_OPT_NO_GRAPH)))
         return FFT_E_ARG;
     const size_t esize = dtype == FFT_C64 ? 8 : 16;
     const int max_t = dtype == FFT_C64 ? FFT_MAX_LOG2N_C64 : FFT_MAX_LOG2N_C128;
@@ -1465,7 +1482,8 @@ int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void 
         a.lines = p->k1.lines;
         a.ntiles = p->k1.ntiles;
         a.pitch = p->k1.pitch;
-        a.log2T = a.log2T1 = p->k1.log2T;
+        a.log2T = p->k1.log2T;
+        a.log2T1 = p->log2W;
         a.conj_in = inv;
         a.conj_out = 0;
         a.xcd_remap = p->k1.remap;
@@ -1478,7 +1496,7 @@ int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void 
         a.ntiles = p->k2.ntiles;
         a.pitch = p->k2.pitch;
         a.log2T = p->k2.log2T;
-        a.log2T1 = p->k1.log2T;
+        a.log2T1 = p->log2W;
         a.conj_in = 0;
         a.conj_out = inv;
         a.xcd_remap = p->k2.remap;

@@ -78,7 +78,7 @@ def test_create_rejects_bad_options():
     for opts, want in cases:
         assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(opts), ctypes.byref(h)) == want
     bad = PlanOpts(0, 0, 0, 0, 0)
-    bad.reserved[1] = 1
+    bad.scratch_width = 3
     assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(PlanOpts(0, 0, 0, 3, 0)),
                                 ctypes.byref(h)) == -9
     # contradictory flags: split and full exchange; persistent and one tile
@@ -91,6 +91,10 @@ def test_create_rejects_bad_options():
     for vpt in (-16, 8, 64):
         assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(PlanOpts(0, 0, 0, 0, 0, vpt)),
                                     ctypes.byref(h)) == -9
+        assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(PlanOpts(0, 0, 0, 0, 0, 0, vpt)),
+                                    ctypes.byref(h)) == -9
+    assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(PlanOpts(0, 0, 0, 0, 0, 0, 0, -4)),
+                                ctypes.byref(h)) == -9
     assert L.fft_plan_create_ex(1024, 1, 0, ctypes.byref(bad), ctypes.byref(h)) == -9
     assert L.fft_plan_create(1024, 1, 0, None) == -4
 

@@ -279,3 +279,19 @@ def test_variant_tile_widths(lf):
             assert max(errs) <= TOL[np.complex64], (_variant_id(v), T1, T2, errs)
             if v["values_per_thread"] == 16:
                 assert_rounding_level(got, base, (_variant_id(v), T1, T2))
+
+
+@pytest.mark.parametrize("t,batch", [(22, 2), (24, 1)])
+def test_scratch_slab_widths(lf, t, batch):
+    """Scratch slabs wider and narrower than pass 1's tile (pass 1 then writes
+    its columns into part of a slab, or several slabs), with 16 or 32 values
+    per thread in pass 2 (split exchange), against the oracle."""
+    x = datagen.signals(1 << t, batch, np.complex64, "normal", 330 + t)
+    ref = oracle.fft_batch(x.astype(np.complex128), -1)
+    for W, vpt2, T1, T2 in ((1, 0, 2, 4), (4, 0, 2, 4), (8, 0, 2, 4), (8, 32, 2, 8), (16, 32, 4, 8),
+                            (2, 32, 4, 8)):
+        announce("slab width W=%d vpt2=%d T=(%d,%d) n=2^%d" % (W, vpt2, T1, T2, t))
+        got = run_plan(lf, x, -1, scratch_width=W, values_per_thread2=vpt2, lines_per_block=T1,
+                       lines_per_block2=T2, flags=2)
+        errs = [oracle.rel_l2(got[b], ref[b]) for b in range(batch)]
+        assert max(errs) <= TOL[np.complex64], (W, vpt2, T1, T2, errs)
