@@ -62,9 +62,11 @@ enum {
     FFT_E_ARG = -9          /* other invalid argument (options, precision mode) */
 };
 
-/* Largest supported log2(n) per element type (two-level lift). */
-#define FFT_MAX_LOG2N_C64 24
-#define FFT_MAX_LOG2N_C128 24
+/* Largest supported log2(n) per element type: one workgroup transforms lines
+ * of up to 2^14 complex64 / 2^13 complex128 points, so transforms up to that
+ * length run in one pass and the two-level lift reaches 2^28 / 2^26. */
+#define FFT_MAX_LOG2N_C64 28
+#define FFT_MAX_LOG2N_C128 26
 
 /*
  * Create a plan for `batch` transforms of length `n` of element type `dtype`.
@@ -145,14 +147,15 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
 
 /*
  * A plan for `count` transforms of uneven power-of-two lengths in one packed
- * buffer: transform i (length lengths[i] = 2^t_i, 1 <= t_i <= the dtype's
- * maximum) occupies elements [off_i, off_i + lengths[i]) with off_i the sum
- * of the earlier lengths.  The lengths are the run-time blocking parameters
- * of one batch: the plan groups equal lengths into classes and covers them
- * with two persistent launches (lengths up to 2^12 in one pass plus pass 1 of
- * the longer ones, then pass 2 of the longer ones; Sections 4.2-4.8 of the
- * paper for the lift), each walking a work list of tiles ordered by class,
- * longest lines first.  fft_execute replays the two launches as one captured
+ * buffer: transform i (length lengths[i] = 2^t_i, 1 <= t_i <= 24) occupies
+ * elements [off_i, off_i + lengths[i]) with off_i the sum of the earlier
+ * lengths.  The lengths are the run-time blocking parameters of one batch:
+ * the plan groups equal lengths into classes.  Lengths up to one workgroup's
+ * line (2^14 complex64, 2^13 complex128) run in one pass, one launch per
+ * class; the longer ones share two persistent launches (pass 1 of every
+ * lifted class, then pass 2; Sections 4.2-4.8 of the paper for the lift),
+ * each walking a work list of tiles ordered by class, longest lines first.
+ * fft_execute replays the two launches as one captured
  * graph per (in, out, sign) triple (up to 16 per plan; then, or when the
  * execute stream is itself being captured, the kernels are launched
  * directly).  opts may be NULL; only flags = FFT_OPT_NO_GRAPH (launch
@@ -279,7 +282,7 @@ int fft_plan_create_tuned(int64_t n, int64_t batch, int dtype, int32_t max_candi
                           fft_tune_result *result);
 
 /* ABI version of this header (major*100 + minor). */
-#define LIFTFFT_ABI_VERSION 105
+#define LIFTFFT_ABI_VERSION 106
 int fft_abi_version(void);
 
 #ifdef __cplusplus

@@ -41,7 +41,12 @@ namespace {
 
 enum Kind { K_SINGLE = 0, K_PASS1 = 1, K_PASS2 = 2 };
 
-constexpr int MAX_LOG2_LINE = 12;          // longest line one workgroup transforms
+constexpr int MAX_LOG2_LINE = 14; // longest line one workgroup transforms (complex64)
+// Longest line per element type: 2^14 complex64 points (1024 threads of 16
+// values, 139 KB of LDS for the complex exchange), 2^13 complex128 points
+// (512 threads).  Two passes then reach 2^28 and 2^26.
+constexpr int max_line(int dtype) { return dtype == 0 ? 14 : 13; }
+template <typename Real> constexpr int max_line_of() { return sizeof(Real) == 4 ? 14 : 13; }
 constexpr int64_t LDS_BUDGET = 160 * 1024; // bytes of LDS per workgroup on gfx950
 
 struct PassArgs {
@@ -418,11 +423,13 @@ struct RaggedClass {
 
 constexpr int RAGGED_THREADS = 512;
 constexpr int RAGGED_P1_MIN = 7, RAGGED_P2_MIN = 6; // shortest lift lines (t >= 13)
+constexpr int RAGGED_LMAX = 12;                     // longest lift line (t <= 24)
+constexpr int RAGGED_MAX_T = 24;
 
 template <typename Real, int KIND, int L>
 __device__ __forceinline__ void ragged_tile(const PassArgs &a, int64_t t, unsigned char *smem) {
     constexpr int LMIN = KIND == K_PASS1 ? RAGGED_P1_MIN : RAGGED_P2_MIN;
-    if constexpr (L >= LMIN && L <= MAX_LOG2_LINE) {
+    if constexpr (L >= LMIN && L <= RAGGED_LMAX) {
         const Tile<Real, (1 << L), 16, KIND, 16, true> w(a, smem);
         w.run_one(t);
     }
@@ -470,7 +477,7 @@ __global__ __launch_bounds__(RAGGED_THREADS, (ragged_min_waves<Real>())) void ra
         a.conj_out = kind == K_PASS2 ? inv : 0;
         const int64_t t = it - rc.item_begin;
         __syncthreads(); // the previous tile's LDS readers are done
-        constexpr auto seq = std::make_integer_sequence<int, MAX_LOG2_LINE + 1>{};
+        constexpr auto seq = std::make_integer_sequence<int, RAGGED_LMAX + 1>{};
         if (kind == K_PASS1) ragged_dispatch<Real, K_PASS1>(log2N, a, t, smem_raw, seq);
         else ragged_dispatch<Real, K_PASS2>(log2N, a, t, smem_raw, seq);
     }
@@ -556,21 +563,23 @@ struct Variant {
     }
 };
 
-template <typename Real, int KIND, int RMAX, int VAR, int LMIN, int L> constexpr KernelFn kernel_entry() {
-    if constexpr (L < LMIN || L < 1) return nullptr;
+template <typename Real, int KIND, int RMAX, int VAR, int LMIN, int LMAX, int L>
+constexpr KernelFn kernel_entry() {
+    if constexpr (L < LMIN || L < 1 || L > LMAX || L > max_line_of<Real>()) return nullptr;
     else
         return &pass_kernel<Real, (1 << L), RMAX, KIND, (VAR & 1) ? 32 : 16, (VAR & 2) != 0, (VAR & 4) != 0,
                             (VAR & 8) != 0>;
 }
 
-template <typename Real, int KIND, int RMAX, int VAR, int LMIN, int... L>
+template <typename Real, int KIND, int RMAX, int VAR, int LMIN, int LMAX, int... L>
 constexpr std::array<KernelFn, sizeof...(L)> kernel_row(std::integer_sequence<int, L...>) {
-    return {{kernel_entry<Real, KIND, RMAX, VAR, LMIN, L>()...}};
+    return {{kernel_entry<Real, KIND, RMAX, VAR, LMIN, LMAX, L>()...}};
 }
 
-template <typename Real, int KIND, int RMAX, int VAR = 0, int LMIN = 1> KernelFn pick(int log2N) {
+template <typename Real, int KIND, int RMAX, int VAR = 0, int LMIN = 1, int LMAX = MAX_LOG2_LINE>
+KernelFn pick(int log2N) {
     static const auto row =
-        kernel_row<Real, KIND, RMAX, VAR, LMIN>(std::make_integer_sequence<int, MAX_LOG2_LINE + 1>{});
+        kernel_row<Real, KIND, RMAX, VAR, LMIN, LMAX>(std::make_integer_sequence<int, MAX_LOG2_LINE + 1>{});
     if (log2N < 1 || log2N > MAX_LOG2_LINE) return nullptr;
     return row[log2N];
 }
@@ -588,20 +597,21 @@ template <typename Real> KernelFn pick_default(int kind, int log2N, int rmax) {
 }
 
 // The other variants exist for complex64 pass kernels with radix 16 and lines
-// of 2^10..2^12 (the lifts of the largest transforms).
-constexpr int VARIANT_LMIN = 10;
+// of 2^10..2^12 (the lifts of the largest transforms); the split exchange,
+// the default at these lengths, also for lines of 2^13 and 2^14.
+constexpr int VARIANT_LMIN = 10, VARIANT_LMAX = 12;
 
 template <int KIND> KernelFn pick_variant(int log2N, const Variant &v) {
     switch (v.code()) {
-    case 1: return pick<float, KIND, 16, 1, VARIANT_LMIN>(log2N);
-    case 2: return pick<float, KIND, 16, 2, VARIANT_LMIN>(log2N);
-    case 3: return pick<float, KIND, 16, 3, VARIANT_LMIN>(log2N);
-    case 4: return pick<float, KIND, 16, 4, VARIANT_LMIN>(log2N);
-    case 5: return pick<float, KIND, 16, 5, VARIANT_LMIN>(log2N);
-    case 6: return pick<float, KIND, 16, 6, VARIANT_LMIN>(log2N);
-    case 7: return pick<float, KIND, 16, 7, VARIANT_LMIN>(log2N);
-    case 8: return pick<float, KIND, 16, 8, VARIANT_LMIN>(log2N);
-    case 10: return pick<float, KIND, 16, 10, VARIANT_LMIN>(log2N);
+    case 1: return pick<float, KIND, 16, 1, VARIANT_LMIN, VARIANT_LMAX>(log2N);
+    case 2: return pick<float, KIND, 16, 2, VARIANT_LMIN, MAX_LOG2_LINE>(log2N);
+    case 3: return pick<float, KIND, 16, 3, VARIANT_LMIN, VARIANT_LMAX>(log2N);
+    case 4: return pick<float, KIND, 16, 4, VARIANT_LMIN, VARIANT_LMAX>(log2N);
+    case 5: return pick<float, KIND, 16, 5, VARIANT_LMIN, VARIANT_LMAX>(log2N);
+    case 6: return pick<float, KIND, 16, 6, VARIANT_LMIN, VARIANT_LMAX>(log2N);
+    case 7: return pick<float, KIND, 16, 7, VARIANT_LMIN, VARIANT_LMAX>(log2N);
+    case 8: return pick<float, KIND, 16, 8, VARIANT_LMIN, VARIANT_LMAX>(log2N);
+    case 10: return pick<float, KIND, 16, 10, VARIANT_LMIN, VARIANT_LMAX>(log2N);
     default: return nullptr; // dense variants exist with 16 values per thread, one tile each
     }
 }
@@ -1055,7 +1065,8 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
         return FFT_E_HIP;
     }
 
-    if (o.log2_p == 0 && t <= MAX_LOG2_LINE) {
+    const int mline = max_line(dtype);
+    if (o.log2_p == 0 && t <= mline) {
         p->passes = 1;
         p->log2q = t;
         if (forced) { // the other variants are pass kernels only
@@ -1072,7 +1083,7 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
         p->passes = 2;
         p->log2q = o.log2_p ? t - o.log2_p : (t + 1) / 2;
         p->log2p = t - p->log2q;
-        if (p->log2q > MAX_LOG2_LINE || p->log2p > MAX_LOG2_LINE) {
+        if (p->log2q > mline || p->log2p > mline) {
             free_plan(p);
             return FFT_E_UNSUPPORTED;
         }
@@ -1177,7 +1188,7 @@ int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const
         o.values_per_thread || o.values_per_thread2 || o.scratch_width || (o.flags & ~int32_t(FFT_OPT_NO_GRAPH)))
         return FFT_E_ARG;
     const size_t esize = dtype == FFT_C64 ? 8 : 16;
-    const int max_t = dtype == FFT_C64 ? FFT_MAX_LOG2N_C64 : FFT_MAX_LOG2N_C128;
+    const int max_t = RAGGED_MAX_T, mline = max_line(dtype);
     // Lengths, packed offsets and the classes of equal length.
     std::vector<std::vector<int64_t>> by_t(max_t + 1);
     int64_t total = 0;
@@ -1264,7 +1275,7 @@ int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const
         const size_t oi = offsets.size();
         offsets.insert(offsets.end(), by_t[t].begin(), by_t[t].end());
         const int64_t cnt = int64_t(by_t[t].size());
-        if (t <= MAX_LOG2_LINE) {
+        if (t <= mline) {
             single_specs.push_back({t, cnt, oi});
             used_line[t] = true;
         } else {
@@ -1290,7 +1301,7 @@ int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const
             tab_off[L] = entries;
             entries += int64_t(1) << L;
         }
-    for (int t = MAX_LOG2_LINE + 1; t <= max_t; ++t)
+    for (int t = mline + 1; t <= max_t; ++t)
         if (!by_t[t].empty()) {
             const int h = (t + 1) / 2;
             hi_off[t] = entries;
@@ -1323,7 +1334,7 @@ int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const
     int rc = FFT_OK;
     for (int L = 1; L <= MAX_LOG2_LINE && rc == FFT_OK; ++L)
         if (tab_off[L] >= 0) rc = gen_table(dtype, tb + tab_off[L] * esize, int64_t(1) << L, 1, L);
-    for (int t = MAX_LOG2_LINE + 1; t <= max_t && rc == FFT_OK; ++t)
+    for (int t = mline + 1; t <= max_t && rc == FFT_OK; ++t)
         if (hi_off[t] >= 0) {
             const int h = (t + 1) / 2;
             rc = gen_table(dtype, tb + hi_off[t] * esize, int64_t(1) << (t - h), int64_t(1) << h, t);
@@ -1649,11 +1660,11 @@ std::vector<fft_plan_opts> tune_candidates(int t, int dtype) {
     const int lq = (t + 1) / 2, lp = t - lq;
     for (int d : {1, -1, 2}) { // splits p = 2^(lp + d); q = 2^(t - lp - d)
         const int l2p = lp + d;
-        if (l2p >= 1 && l2p < t && l2p <= MAX_LOG2_LINE && t - l2p <= MAX_LOG2_LINE) add(l2p, 0, 0, 0, 0, 0);
+        if (l2p >= 1 && l2p < t && l2p <= max_line(dtype) && t - l2p <= max_line(dtype)) add(l2p, 0, 0, 0, 0, 0);
     }
-    if (t <= MAX_LOG2_LINE && lp >= 1) add(lp, 0, 0, 0, 0, 0); // two passes below the threshold
+    if (t <= max_line(dtype) && lp >= 1) add(lp, 0, 0, 0, 0, 0); // two passes below the threshold
     add(0, 2, 0, 0, 0, 0);
-    if (t > MAX_LOG2_LINE || t >= 2) {
+    if (t >= 2) {
         const int variants[][2] = {{FFT_OPT_FULL_EXCHANGE, 16}, {FFT_OPT_SPLIT_EXCHANGE, 16},
                                    {FFT_OPT_SPLIT_EXCHANGE, 32}, {0, 32},
                                    {FFT_OPT_PERSISTENT, 16}, {FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_DENSE, 16}};

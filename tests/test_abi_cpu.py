@@ -60,7 +60,7 @@ def test_strerror_covers_codes():
 @pytest.mark.parametrize("n,batch,dtype,want", [
     (0, 1, 0, -1), (1, 1, 0, -1), (3, 1, 0, -1), (1000, 1, 0, -1), (-8, 1, 0, -1),
     (1024, 0, 0, -1), (1024, -5, 1, -1), (1024, 1, 2, -2), (1024, 1, -1, -2),
-    (1 << 25, 1, 0, -8), (1 << 30, 1, 1, -8), (1 << 20, 1 << 60, 0, -1),
+    (1 << 29, 1, 0, -8), (1 << 27, 1, 1, -8), (1 << 30, 1, 1, -8), (1 << 20, 1 << 60, 0, -1),
 ])
 def test_create_validation(n, batch, dtype, want):
     L = _lib()
@@ -126,6 +126,7 @@ def test_create_many_validation():
         assert L.fft_plan_create_many(arr(*bad), 2, 0, None, ctypes.byref(h)) == -1, bad
     assert L.fft_plan_create_many(arr(8, 1 << 25), 2, 0, None, ctypes.byref(h)) == -8
     assert L.fft_plan_create_many(arr(8, 1 << 25), 2, 1, None, ctypes.byref(h)) == -8
+    assert L.fft_plan_create_many(arr(8, 1 << 29), 2, 0, None, ctypes.byref(h)) == -8
     # the packed buffer must stay below 2^32 bytes (32-bit buffer descriptors)
     big = arr(*([1 << 24] * 32))
     assert L.fft_plan_create_many(big, 32, 0, None, ctypes.byref(h)) == -8

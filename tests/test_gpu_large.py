@@ -1,0 +1,123 @@
+"""Transforms beyond 2^24, up to the two-level limit (2^28 complex64, 2^26
+complex128: pass lines of up to 2^14 / 2^13 points), and single-pass lines of
+2^13 and 2^14 points.
+
+At 2^25 and 2^26 the whole output is compared with the FP64 oracle.  At
+2^27 and 2^28 the oracle would take minutes, so the checks are properties
+that hold at any size: a pure tone (the transform is n at one bin and 0
+elsewhere), the round trip F+ F- x = n x, and outputs at sampled frequencies
+evaluated one by one from the definition in FP64 with the exponent j*k
+reduced mod n in integers.
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from gpu_util import announce, require_gpu, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def lf(torch):
+    import paper_0811_2535_amd as lf
+    return lf
+
+
+def dft_at(x, k, sign):
+    """X_k = sum_j x_j exp(sign 2 pi i (j k mod n) / n) in FP64, in chunks."""
+    n = x.size
+    acc = 0j
+    step = 1 << 22
+    for j0 in range(0, n, step):
+        j = np.arange(j0, min(n, j0 + step), dtype=np.int64)
+        e = (j * np.int64(k)) % n
+        acc += np.sum(x[j0:j0 + j.size].astype(np.complex128) * np.exp(sign * 2j * np.pi * (e / n)))
+    return acc
+
+
+@pytest.mark.parametrize("t,dtype", [(13, np.complex64), (14, np.complex64), (13, np.complex128)])
+def test_longest_single_pass_lines(lf, torch, t, dtype):
+    n, batch = 1 << t, 6
+    plan = lf.Plan(n, batch, torch.complex64 if dtype == np.complex64 else torch.complex128)
+    assert plan.info()["passes"] == 1
+    plan.destroy()
+    x = datagen.signals(n, batch, dtype, "normal", 600 + t)
+    tol = 1e-6 if dtype == np.complex64 else 1e-12
+    for sign in (-1, 1):
+        announce("single-pass n=2^%d %s sign=%d" % (t, np.dtype(dtype).name, sign))
+        p = lf.Plan(n, batch, torch.complex64 if dtype == np.complex64 else torch.complex128)
+        xd = to_dev(x)
+        y = torch.full_like(xd, float("nan"))
+        p.execute(xd, y, sign)
+        torch.cuda.synchronize()
+        p.destroy()
+        ref = oracle.fft_batch(x.astype(np.complex128), sign)
+        got = to_np(y)
+        errs = [oracle.rel_l2(got[b], ref[b]) for b in range(batch)]
+        assert max(errs) <= tol, (t, sign, errs)
+
+
+@pytest.mark.parametrize("t,dtype", [(25, np.complex64), (26, np.complex64), (25, np.complex128),
+                                     (26, np.complex128)])
+def test_full_oracle_beyond_2p24(lf, torch, t, dtype):
+    n = 1 << t
+    tdt = torch.complex64 if dtype == np.complex64 else torch.complex128
+    plan = lf.Plan(n, 1, tdt)
+    info = plan.info()
+    assert info["passes"] == 2 and info["log2_q"] == (t + 1) // 2
+    x_np = datagen.signals(n, 1, dtype, "normal", 700 + t)
+    x = to_dev(x_np)
+    y = torch.empty_like(x)
+    announce("large n=2^%d %s forward" % (t, np.dtype(dtype).name))
+    plan.execute(x, y, -1)
+    torch.cuda.synchronize()
+    ref = oracle.fft(x_np[0].astype(np.complex128), -1)
+    err = oracle.rel_l2(to_np(y)[0], ref)
+    assert err <= (1e-6 if dtype == np.complex64 else 1e-12), err
+    plan.destroy()
+
+
+@pytest.mark.parametrize("t", [27, 28])
+def test_properties_at_two_level_limit(lf, torch, t):
+    n = 1 << t
+    plan = lf.Plan(n, 1, torch.complex64)
+    assert plan.info()["log2_q"] == (t + 1) // 2
+    # pure tone x_j = w_n^(a j): the forward transform is n at bin a
+    a = 123457 % n
+    j = torch.arange(n, device="cuda", dtype=torch.int64)
+    ang = (j * a % n).to(torch.float64) * (2 * np.pi / n)
+    x = torch.complex(torch.cos(ang), torch.sin(ang)).to(torch.complex64)
+    del ang, j
+    y = torch.empty_like(x)
+    announce("limit n=2^%d tone" % t)
+    plan.execute(x, y, -1)
+    torch.cuda.synchronize()
+    expect = torch.zeros_like(y)
+    expect[a] = n
+    err = float(torch.linalg.vector_norm((y - expect).to(torch.complex128)) / n)
+    assert err <= 1e-6, err
+    # round trip and sampled frequencies on N(0,1) input
+    x_np = datagen.signals(n, 1, np.complex64, "normal", 800 + t)[0]
+    x = to_dev(x_np)
+    announce("limit n=2^%d round trip" % t)
+    plan.execute(x, y, -1)
+    z = torch.empty_like(y)
+    plan.execute(y, z, 1)
+    torch.cuda.synchronize()
+    rt = float(torch.linalg.vector_norm((z / n - x).to(torch.complex128)) / torch.linalg.vector_norm(
+        x.to(torch.complex128)))
+    assert rt <= 2e-6, rt
+    y_np = to_np(y)
+    rms = np.sqrt(np.mean(np.abs(y_np.astype(np.complex128)) ** 2))
+    for k in datagen.sample_indices(n, 3, seed=t):
+        announce("limit n=2^%d sample k=%d" % (t, k))
+        ref = dft_at(x_np, int(k), -1)
+        assert abs(y_np[k] - ref) <= 1e-5 * rms, (int(k), complex(y_np[k]), ref, rms)
+    plan.destroy()
