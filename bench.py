@@ -192,7 +192,8 @@ def measure_fwd_bwd(torch, lf, datagen, reps: int = 5) -> dict:
 
 def measure_ragged(torch, lf, datagen, reps: int = 10) -> dict:
     """Batched uneven lengths: 4096 complex64 transforms with k ~ U{8..16}
-    (seed 3), U[-1,1], packed back to back; the plan's graph launch against
+    (seed 3), U[-1,1], packed back to back; the plan (direct launches, and
+    replayed as a captured graph) against
     (a) one single-length batched plan per length class (each class gathered
     into its own contiguous buffer beforehand, not timed) and (b) one plain
     launch per transform."""
@@ -205,19 +206,22 @@ def measure_ragged(torch, lf, datagen, reps: int = 10) -> dict:
     sets = 3  # rotated so that no input is still in the last-level cache
     xs = [torch.from_numpy(x_np).to(dev) for _ in range(sets)]
     ys = [torch.empty_like(xs[0]) for _ in range(sets)]
-    plan = lf.Plan.uneven(lengths, torch.complex64, graph=True)
-    for i in range(sets):
-        plan.execute(xs[i], ys[i], -1)
-    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for i in range(reps):
-        plan.execute(xs[i % sets], ys[i % sets], -1)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_graph = e0.elapsed_time(e1) / reps
-    info = plan.info()
-    plan.destroy()
+    ms_mode = {}
+    for graph in (False, True):
+        plan = lf.Plan.uneven(lengths, torch.complex64, graph=graph)
+        for i in range(sets):
+            plan.execute(xs[i], ys[i], -1)
+        torch.cuda.synchronize()
+        e0.record()
+        for i in range(reps):
+            plan.execute(xs[i % sets], ys[i % sets], -1)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_mode[graph] = e0.elapsed_time(e1) / reps
+        info = plan.info()
+        plan.destroy()
+    ms_direct, ms_graph = ms_mode[False], ms_mode[True]
 
     # (a) per-class batched plans on contiguous class buffers.
     offs = np.concatenate([[0], np.cumsum(lengths)[:-1]])
@@ -257,17 +261,53 @@ def measure_ragged(torch, lf, datagen, reps: int = 10) -> dict:
     for pl in plans.values():
         pl.destroy()
     flops = sum(5.0 * ln * math.log2(ln) for ln in lengths)
-    alg_bytes = sum((16 if ln <= 4096 else 32) * ln for ln in lengths)
+    alg_bytes = sum((16 if ln <= 16384 else 32) * ln for ln in lengths)  # one pass up to 2^14
     return {"workload": "4096 c64 transforms, n = 2^k with k ~ U{8..16} (seed 3), packed, forward",
             "elements": total, "length_classes": info["length_classes"],
-            "ms_graph": round(ms_graph, 4),
-            "gflops": round(flops / (ms_graph * 1e-3) / 1e9, 1),
-            "hbm_gbps_algorithmic": round(alg_bytes / (ms_graph * 1e-3) / 1e9, 1),
+            "ms": round(ms_direct, 4), "ms_graph_replay": round(ms_graph, 4),
+            "gflops": round(flops / (ms_direct * 1e-3) / 1e9, 1),
+            "hbm_gbps_algorithmic": round(alg_bytes / (ms_direct * 1e-3) / 1e9, 1),
             "ms_per_class_batched_plans": round(ms_classes, 4),
             "ms_one_launch_per_transform": round(ms_each, 4),
-            "speedup_vs_per_class": round(ms_classes / ms_graph, 3),
-            "speedup_vs_per_transform": round(ms_each / ms_graph, 3),
+            "speedup_vs_per_class": round(ms_classes / ms_direct, 3),
+            "speedup_vs_per_transform": round(ms_each / ms_direct, 3),
             "grid": [info["grid_pass1"], info["grid_pass2"]]}
+
+
+def measure_precision(torch, lf, datagen, reps: int = 5) -> dict:
+    """Precision forms on 256 transforms of 2^20 complex64 (N(0,1), seed 4),
+    lifted 4096 x 256 so every stage is radix 16: FP32 stages on the vector
+    units against radix-16 stages on the matrix cores with FP16 / BF16 pairs.
+    Error: relative L2 of transform 0 against the FP64 oracle."""
+    import numpy as np
+
+    import oracle
+    n, batch = 1 << 20, 256
+    dev = torch.device("cuda:0")
+    x_np = datagen.signals(n, batch, np.complex64, "normal", 4)
+    x = torch.from_numpy(x_np).to(dev)
+    y = torch.empty_like(x)
+    ref0 = oracle.fft(x_np[0].astype(np.complex128), -1)
+    plan = lf.Plan(n, batch, torch.complex64, log2_p=8)
+    out = {"workload": "256 x 2^20 c64 forward, lift 4096 x 256 (all stages radix 16)"}
+    flops = 5.0 * n * math.log2(n) * batch
+    for mode in ("fp32", "f16x2", "bf16x2"):
+        plan.set_precision(mode)
+        plan.execute(x, y, -1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            plan.execute(x, y, -1)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        err = oracle.rel_l2(y[0].cpu().numpy(), ref0)
+        out[mode] = {"ms": round(ms, 4), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+                     "hbm_gbps_algorithmic": round(32 * n * batch / (ms * 1e-3) / 1e9, 1),
+                     "rel_l2_transform0": float("%.3g" % err)}
+    plan.destroy()
+    return out
 
 
 def main() -> int:
@@ -279,7 +319,8 @@ def main() -> int:
     ap.add_argument("--sets", type=int, default=4, help="buffer sets rotated between transforms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the differentiation-form and uneven-batch measurements")
+                    help="skip the differentiation-form, uneven-batch, precision-form and "
+                         "autotuner measurements")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary from two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of this benchmark and exit")
@@ -440,6 +481,8 @@ def main() -> int:
         lf.clear_plan_cache()
         print("[bench] batched uneven lengths, 4096 transforms", file=sys.stderr, flush=True)
         result["ragged"] = measure_ragged(torch, lf, datagen)
+        print("[bench] precision forms, 256 x 2^20", file=sys.stderr, flush=True)
+        result["precision"] = measure_precision(torch, lf, datagen)
         print("[bench] autotuner on the headline shape", file=sys.stderr, flush=True)
         tplan, tres = lf.Plan.tuned(n, 1, torch.complex64, max_candidates=48)
         tplan.destroy()

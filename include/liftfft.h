@@ -155,16 +155,18 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
  * class; the longer ones share two persistent launches (pass 1 of every
  * lifted class, then pass 2; Sections 4.2-4.8 of the paper for the lift),
  * each walking a work list of tiles ordered by class, longest lines first.
- * fft_execute replays the two launches as one captured
- * graph per (in, out, sign) triple (up to 16 per plan; then, or when the
- * execute stream is itself being captured, the kernels are launched
- * directly).  opts may be NULL; only flags = FFT_OPT_NO_GRAPH (launch
- * directly) is accepted, anything else returns FFT_E_ARG.
+ * fft_execute launches them directly on the execute stream.  With
+ * flags = FFT_OPT_GRAPH it instead replays them as one captured graph per
+ * (in, out, sign) triple (captured on a private stream the first time; up to
+ * 16 per plan; then, or when the execute stream is itself being captured,
+ * the kernels are launched directly).  Replays measure a few percent slower
+ * than direct launches on MI355X, hence the default.  opts may be NULL;
+ * only flags = FFT_OPT_GRAPH is accepted, anything else returns FFT_E_ARG.
  * Errors: FFT_E_NULL (lengths or plan_out NULL), FFT_E_SIZE (count < 1, a
  * length not a power of two >= 2), FFT_E_UNSUPPORTED (a length above the
  * maximum, or a packed buffer of 2^32 bytes or more).
  */
-enum { FFT_OPT_NO_GRAPH = 64 };
+enum { FFT_OPT_GRAPH = 64 };
 int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const fft_plan_opts *opts,
                          fft_plan **plan_out);
 
@@ -282,7 +284,7 @@ int fft_plan_create_tuned(int64_t n, int64_t batch, int dtype, int32_t max_candi
                           fft_tune_result *result);
 
 /* ABI version of this header (major*100 + minor). */
-#define LIFTFFT_ABI_VERSION 106
+#define LIFTFFT_ABI_VERSION 107
 int fft_abi_version(void);
 
 #ifdef __cplusplus

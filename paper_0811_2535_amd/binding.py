@@ -49,7 +49,7 @@ FFT_OPT_FULL_EXCHANGE = 4
 FFT_OPT_PERSISTENT = 8
 FFT_OPT_ONE_TILE = 16
 FFT_OPT_DENSE = 32
-FFT_OPT_NO_GRAPH = 64
+FFT_OPT_GRAPH = 64
 
 
 class PlanOpts(ctypes.Structure):
@@ -174,7 +174,7 @@ class Plan:
         return self, res.as_dict()
 
     @classmethod
-    def uneven(cls, lengths, dtype=torch.complex64, graph: bool = True) -> "Plan":
+    def uneven(cls, lengths, dtype=torch.complex64, graph: bool = False) -> "Plan":
         """A plan for transforms of the given power-of-two lengths packed back
         to back in one buffer (fft_plan_create_many); ``self.offsets`` holds
         each transform's first element."""
@@ -184,7 +184,7 @@ class Plan:
         arr = (ctypes.c_int64 * max(1, len(lens)))(*lens)
         self.dtype_code = dtype_code(dtype)
         self.torch_dtype = torch.complex64 if self.dtype_code == FFT_C64 else torch.complex128
-        opts = PlanOpts(0, 0, 0, 0, 0 if graph else FFT_OPT_NO_GRAPH)
+        opts = PlanOpts(0, 0, 0, 0, FFT_OPT_GRAPH if graph else 0)
         rc = lib().fft_plan_create_many(arr, len(lens), self.dtype_code, ctypes.byref(opts),
                                         ctypes.byref(self._h))
         _check(rc, "fft_plan_create_many(count=%d)" % len(lens))

@@ -1185,7 +1185,7 @@ int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const
     memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
     if (o.log2_p || (o.radix && o.radix != 16) || o.lines_per_block || o.lines_per_block2 ||
-        o.values_per_thread || o.values_per_thread2 || o.scratch_width || (o.flags & ~int32_t(FFT_OPT_NO_GRAPH)))
+        o.values_per_thread || o.values_per_thread2 || o.scratch_width || (o.flags & ~int32_t(FFT_OPT_GRAPH)))
         return FFT_E_ARG;
     const size_t esize = dtype == FFT_C64 ? 8 : 16;
     const int max_t = RAGGED_MAX_T, mline = max_line(dtype);
@@ -1218,7 +1218,7 @@ int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const
     p->dtype = dtype;
     p->esize = esize;
     p->radix = 16;
-    p->use_graph = !(o.flags & FFT_OPT_NO_GRAPH);
+    p->use_graph = (o.flags & FFT_OPT_GRAPH) != 0;
     auto fail = [&](int rc) {
         free_plan(p);
         return rc;

@@ -41,7 +41,7 @@ def oracle_ragged(x, lengths, sign):
     return out
 
 
-def run_ragged(lf, x_np, lengths, sign, graph=True, repeat=1):
+def run_ragged(lf, x_np, lengths, sign, graph=False, repeat=1):
     import torch
     dt = torch.complex64 if x_np.dtype == np.complex64 else torch.complex128
     plan = lf.Plan.uneven(lengths, dt, graph=graph)
@@ -68,8 +68,9 @@ def check_ragged(got, ref, lengths, tol, what):
 
 @pytest.mark.parametrize("dtype", [np.complex64, np.complex128], ids=["c64", "c128"])
 def test_every_length_class(lf, dtype):
-    """Every length 2^1..2^16 (single-pass classes up to 2^12, lifted ones
-    above) in one packed batch with random extra lengths, both signs."""
+    """Every length 2^1..2^16 (single-pass classes up to 2^14 complex64 /
+    2^13 complex128, lifted ones above) in one packed batch with random extra
+    lengths, both signs."""
     ks = list(datagen.uneven_log2_lengths(160, 1, 16, seed=31)) + list(range(1, 17))
     lengths = [1 << int(k) for k in ks]
     x = datagen.ragged_signals(lengths, dtype, "uniform", 32)
@@ -89,7 +90,7 @@ def test_config3_full(lf):
     for sign in (-1, 1):
         announce("ragged config3 sign=%d elements=%d" % (sign, len(x)))
         got, info = run_ragged(lf, x, lengths, sign)
-        assert info["length_classes"] == 9 and info["graph_launch"] == 1
+        assert info["length_classes"] == 9 and info["graph_launch"] == 0
         check_ragged(got, oracle_ragged(x, lengths, sign), lengths, 1e-6, ("config3", sign))
 
 
