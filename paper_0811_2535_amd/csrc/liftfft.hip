@@ -2,21 +2,28 @@
 // for gfx950.  The ABI is declared (and documented) in include/liftfft.h.
 //
 // Kernels (all in this file, device code in fft_engine.hpp):
-//   pass_kernel<K_SINGLE>  n <= 4096: one workgroup tile holds whole
-//                          transforms; natural order in and out.
+//   pass_kernel<K_SINGLE>  n up to one workgroup's line (2^14 complex64,
+//                          2^13 complex128): a tile holds whole transforms;
+//                          natural order in and out.
 //   pass_kernel<K_PASS1>   block phase of the lift n = p*q (Section 4.2-4.7 of
 //                          the paper, Fig. 4.8): for each j1 < p the q-point
 //                          transform over j2 of x[j1 + p*j2]; then the
 //                          inter-phase weight w_n^(-j1*k2) (the paper's
 //                          weightcyclic factors, Section 4.5, Fig. 4.4) and a
-//                          store into the tiled scratch array
-//                          S[j1/T1][k2][j1%T1] (the block-to-cyclic
+//                          store into the slabs S[j1/W][k2][j1%W] of the
+//                          scratch array (the block-to-cyclic
 //                          redistribution, Fig. 5.3 / Fig. 5.9).
 //   pass_kernel<K_PASS2>   cyclic phase (Section 4.6, Fig. 4.6): for each
 //                          k2 < q the p-point transform over j1 of S, stored
 //                          as X[k2 + q*k1] (natural order, the
 //                          cyclic-to-centralized gather of Fig. 5.5).
+//                          Variants of the pass kernels: values per thread,
+//                          split exchange, persistent prefetch, register cap,
+//                          and radix-16 stages on the matrix cores.
+//   ragged_kernel          persistent pass 1 / pass 2 over the lifted length
+//                          classes of a packed batch of uneven lengths.
 //   twiddle_table_kernel   FP64 generation of the weight tables.
+//   fill_pattern_kernel, compare_kernel   the autotuner's input and check.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
