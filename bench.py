@@ -36,10 +36,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c64_n2p24.txt")
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources with comments and blank lines removed, so
+    that counter values stay attached to the code they were taken on (and
+    only to it)."""
+    import re
     h = hashlib.sha256()
     for f in ("liftfft.hip", "fft_engine.hpp"):
-        with open(os.path.join(ROOT, "paper_0811_2535_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_0811_2535_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        text = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(text.encode())
     return h.hexdigest()[:16]
 
 
