@@ -71,8 +71,9 @@ enum {
 /*
  * Create a plan for `batch` transforms of length `n` of element type `dtype`.
  * Validates the arguments, chooses the lift (single pass when n fits one
- * workgroup, else p x q with q >= p), allocates the scratch array (n*batch
- * elements, two-pass plans only) and the twiddle tables, and fills the tables
+ * workgroup, else p x q with q >= p, or the three-level lift where it is
+ * the faster one), allocates the scratch array (n*batch elements, lifted
+ * plans only) and the twiddle tables, and fills the tables
  * on the current device with an FP64 kernel (each entry computed directly
  * from its integer exponent, rounded once to the element type).  Synchronous.
  * On success *plan_out owns the plan (release with fft_plan_destroy); on
@@ -108,6 +109,13 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out);
  *                     FFT_OPT_DENSE: pass kernels capped at 64 VGPRs so that
  *                     two 1024-thread workgroups fit one CU (16 values per
  *                     thread, one tile per workgroup only).
+ *                     FFT_OPT_TWO_LEVEL / FFT_OPT_THREE_LEVEL: force the
+ *                     two-level lift p x q (two passes) / the three-level
+ *                     lift (see below) instead of the library's choice.
+ *                     FFT_OPT_THREE_LEVEL takes no two-level options
+ *                     (log2_p, lines_per_block2, values_per_thread2,
+ *                     scratch_width: FFT_E_ARG); lines_per_block then sets
+ *                     the lines per workgroup of all three passes.
  *   values_per_thread complex values each thread holds in the pass kernels:
  *                     0 (default), 16 or 32.
  *   values_per_thread2  the same for pass 2 only (0 = as values_per_thread).
@@ -120,6 +128,19 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out);
  * Kernel variants other than the defaults exist for complex64 two-pass
  * plans with radix 16 and pass lines of 2^10..2^12; asking for one elsewhere
  * returns FFT_E_UNSUPPORTED.  Contradictory flags return FFT_E_ARG.
+ *
+ * Three-level lift (dimension lifting, section 1, taken one level further):
+ * n = n1 n2 n3 with x viewed as an n3 x n2 x n1 array (n1 contiguous),
+ * j = j1 + n1 j2 + n1 n2 j3 and k = k3 + n3 k2 + n2 n3 k1.  Pass A: n3-point
+ * transforms along j3, times w_n^(s n1 j2 k3), written to `out` in the
+ * input's layout; pass B: n2-point transforms along j2, times
+ * w_n^(s j1 (k3 + n3 k2)), written to the scratch array in the same layout;
+ * pass C: n1-point transforms of the contiguous rows, written to `out` in
+ * natural order.  Each workgroup takes adjacent lines of the contiguous axis,
+ * so every pass reads and writes runs of at least 128 bytes.  Factors:
+ * log2 n3 = ceil(t/3), log2 n1 = ceil((t - log2 n3)/2), n2 the rest; each
+ * between 2^5 and 2^11 (15 <= t), radix 16, default or split-exchange
+ * kernels; otherwise FFT_E_UNSUPPORTED.
  */
 enum {
     FFT_OPT_NO_XCD_REMAP = 1,
@@ -127,7 +148,9 @@ enum {
     FFT_OPT_FULL_EXCHANGE = 4,
     FFT_OPT_PERSISTENT = 8,
     FFT_OPT_ONE_TILE = 16,
-    FFT_OPT_DENSE = 32
+    FFT_OPT_DENSE = 32,
+    FFT_OPT_TWO_LEVEL = 128,
+    FFT_OPT_THREE_LEVEL = 256
 };
 typedef struct fft_plan_opts {
     int32_t log2_p;
@@ -223,6 +246,12 @@ typedef struct fft_plan_info {
     int32_t variant_pass1, variant_pass2;
     int32_t length_classes, graph_launch;
     int32_t precision, reserved0;
+    /* levels: passes of a single-length plan (1, 2 or 3; 0 for uneven
+     * batches).  Three-level plans: log2 of n1, n2, n3 (log2_p = log2_q = 0)
+     * and pass C's launch in the *_pass3 fields (A and B in pass1, pass2). */
+    int32_t levels, log2_n1, log2_n2, log2_n3;
+    int32_t lines_per_block_pass3, grid_pass3, threads_pass3, reserved1;
+    int64_t lds_bytes_pass3;
 } fft_plan_info;
 
 int fft_plan_get_info(const fft_plan *plan, fft_plan_info *info);
@@ -248,11 +277,13 @@ int fft_plan_set_precision(fft_plan *plan, int mode);
  * Per-kernel timing, for benchmarks.  While enabled, fft_execute records a
  * HIP event before and after each kernel it launches, on the execute stream;
  * fft_plan_read_timing synchronises on the last recorded event and returns,
- * for pass k (k = 0, 1), the summed duration in milliseconds and the launch
- * count since the last reset.  Disabled by default (no events recorded).
+ * for pass k (k = 0, 1, 2), the summed duration in milliseconds and the
+ * launch count since the last reset (zero for passes the plan does not
+ * have).  Both arrays hold three entries.  Disabled by default (no events
+ * recorded).
  */
 int fft_plan_set_timing(fft_plan *plan, int enable);
-int fft_plan_read_timing(fft_plan *plan, double ms_out[2], int64_t launches_out[2],
+int fft_plan_read_timing(fft_plan *plan, double ms_out[3], int64_t launches_out[3],
                          int reset);
 
 /*
@@ -284,7 +315,7 @@ int fft_plan_create_tuned(int64_t n, int64_t batch, int dtype, int32_t max_candi
                           fft_tune_result *result);
 
 /* ABI version of this header (major*100 + minor). */
-#define LIFTFFT_ABI_VERSION 107
+#define LIFTFFT_ABI_VERSION 108
 int fft_abi_version(void);
 
 #ifdef __cplusplus

@@ -50,6 +50,8 @@ FFT_OPT_PERSISTENT = 8
 FFT_OPT_ONE_TILE = 16
 FFT_OPT_DENSE = 32
 FFT_OPT_GRAPH = 64
+FFT_OPT_TWO_LEVEL = 128
+FFT_OPT_THREE_LEVEL = 256
 
 
 class PlanOpts(ctypes.Structure):
@@ -85,7 +87,12 @@ class PlanInfo(ctypes.Structure):
                 ("scratch_bytes", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
                 ("variant_pass1", ctypes.c_int32), ("variant_pass2", ctypes.c_int32),
                 ("length_classes", ctypes.c_int32), ("graph_launch", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("log2_n1", ctypes.c_int32),
+                ("log2_n2", ctypes.c_int32), ("log2_n3", ctypes.c_int32),
+                ("lines_per_block_pass3", ctypes.c_int32), ("grid_pass3", ctypes.c_int32),
+                ("threads_pass3", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("lds_bytes_pass3", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -122,8 +129,8 @@ def lib():
             L.fft_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
             L.fft_plan_set_timing.argtypes = [vp, i32]
             L.fft_plan_set_precision.argtypes = [vp, i32]
-            L.fft_plan_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double * 2),
-                                               ctypes.POINTER(ctypes.c_int64 * 2), i32]
+            L.fft_plan_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double * 3),
+                                               ctypes.POINTER(ctypes.c_int64 * 3), i32]
             for name in ("fft_plan_create", "fft_plan_create_ex", "fft_plan_create_many",
                          "fft_plan_create_tuned", "fft_plan_set_precision", "fft_execute",
                          "fft_plan_destroy", "fft_plan_get_info", "fft_plan_set_timing",
@@ -251,11 +258,13 @@ class Plan:
         _check(lib().fft_plan_set_timing(self.handle, int(bool(enable))), "fft_plan_set_timing")
 
     def read_timing(self, reset: bool = True):
-        ms = (ctypes.c_double * 2)()
-        cnt = (ctypes.c_int64 * 2)()
+        """([ms per pass] , [launches per pass]) summed since the last reset,
+        three entries each (passes the plan does not have read zero)."""
+        ms = (ctypes.c_double * 3)()
+        cnt = (ctypes.c_int64 * 3)()
         _check(lib().fft_plan_read_timing(self.handle, ctypes.byref(ms), ctypes.byref(cnt),
                                           int(bool(reset))), "fft_plan_read_timing")
-        return [ms[0], ms[1]], [cnt[0], cnt[1]]
+        return list(ms), list(cnt)
 
     def destroy(self) -> None:
         if self._h:

@@ -257,24 +257,29 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), short(0), int(bytes),
                                              0x00020000);
 }
+// AUX is the instruction's cache-policy field (0: default; on gfx950 bit 1
+// marks the access non-temporal, i.e. streamed past the caches' normal
+// retention).
+template <int AUX = 0>
 __device__ __forceinline__ float2 buf_load(const float2 *, rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
 }
+template <int AUX = 0>
 __device__ __forceinline__ double2 buf_load(const double2 *, rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
 }
-__device__ __forceinline__ void buf_store(float2 v, rsrc_t r, uint32_t voff, uint32_t soff) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+template <int AUX = 0> __device__ __forceinline__ void buf_store(float2 v, rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, AUX);
 }
 // A 16-byte element is stored as two 8-byte stores: with a single 16-byte
 // buffer store, the compiler here lets the next VALU instruction overwrite
 // the store's first data register without a wait state, and the stored
 // first dword then intermittently holds the new value.
 // (The empty asm statement keeps the two stores from being merged back.)
-__device__ __forceinline__ void buf_store(double2 v, rsrc_t r, uint32_t voff, uint32_t soff) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v.x), r, voff, soff, 0);
+template <int AUX = 0> __device__ __forceinline__ void buf_store(double2 v, rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v.x), r, voff, soff, AUX);
     __asm__ volatile("" ::: "memory");
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v.y), r, voff + 8, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v.y), r, voff + 8, soff, AUX);
 }
 // Element index held by register slot s on entry (first-stage layout) or on
 // exit (last-stage layout) relative to the thread's j: slot i*R + r <->

@@ -46,7 +46,7 @@ using namespace liftfft;
 
 namespace {
 
-enum Kind { K_SINGLE = 0, K_PASS1 = 1, K_PASS2 = 2 };
+enum Kind { K_SINGLE = 0, K_PASS1 = 1, K_PASS2 = 2, K_AXIS = 3 };
 
 constexpr int MAX_LOG2_LINE = 14; // longest line one workgroup transforms (complex64)
 // Longest line per element type: 2^14 complex64 points (1024 threads of 16
@@ -74,6 +74,15 @@ struct PassArgs {
     int32_t pitch;  // exchange line pitch, in exchange elements
     const int64_t *offsets; // packed uneven batch: first element of each transform (else b*n)
     int64_t total;          // packed uneven batch: elements in the buffer
+    // Axis passes of a three-level lift (K_AXIS).  Line l of a transform is
+    // (lm, ld) = (l mod 2^ax_log2U, l div 2^ax_log2U); element i of the line
+    // sits at (lm << ax_in[0]) + (ld << ax_in[1]) + (i << ax_in[2]) and
+    // result k goes to the same form over ax_out.  ax_tw selects the fused
+    // weight w_n^-(u (k0 + 2^ax_log2m k)): 0 none, 1 u = ld 2^ax_log2U and
+    // k0 = 0, 2 u = lm and k0 = ld.
+    int32_t ax_log2U, ax_log2L; // fast line axis; lines per transform
+    int32_t ax_in[3], ax_out[3];
+    int32_t ax_tw, ax_log2m;
 };
 
 // Workgroup g's k-th tile, or -1.  Workgroups are dispatched round-robin over
@@ -105,6 +114,11 @@ template <typename Real, int EMAX, bool PERSIST> constexpr int max_threads() {
 // Minimum waves per SIMD the register allocation must allow: 8 (64 VGPRs,
 // two 1024-thread workgroups per CU) for the dense variants, else 1.
 template <bool DENSE> constexpr int min_waves() { return DENSE ? 8 : 1; }
+
+// Cache policies of the lifted passes' global accesses (the AUX field of the
+// buffer instructions): pass-1 column loads, pass-1 scratch stores, pass-2
+// scratch loads, pass-2 natural-order stores.
+constexpr int CP_LOAD1 = 0, CP_STORE1 = 0, CP_LOAD2 = 0, CP_STORE2 = 0;
 
 // The work of one workgroup on tiles of T lines of one kernel shape:
 // loads, the pass-1 weights, the stage loop and the stores.  Shared by the
@@ -180,6 +194,16 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
         }
     }
 
+    // Axis passes: byte offset of this thread's element j of line c, within
+    // its transform, for the stride triple `st` (fast line axis, slow line
+    // axis, transform axis).  The plan keeps T | 2^ax_log2U, so the tile's
+    // lines share one ld.
+    __device__ __forceinline__ uint32_t axis_lane(int64_t line0, const int32_t *st) const {
+        const uint32_t l = uint32_t(line0 & ((int64_t(1) << a.ax_log2L) - 1));
+        const uint32_t lm = l & ((1u << a.ax_log2U) - 1), ld = l >> a.ax_log2U;
+        return (((lm + uint32_t(c)) << st[0]) + (ld << st[1]) + (uint32_t(j) << st[2])) * ES;
+    }
+
     // Data loads of the tile starting at line0: a buffer descriptor, one
     // 32-bit lane offset, and a uniform per-slot offset.  Raw values: the
     // conjugation of sign +1 is applied by the caller, so that a prefetch is
@@ -202,7 +226,13 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
             const uint32_t lane = (uint32_t(c) + (uint32_t(j) << a.log2p)) * ES;
 #pragma unroll
             for (int s = 0; s < E; ++s)
-                v[s] = buf_load(in, src, lane, (uint32_t(slot_off<N, E, R0>(s)) << a.log2p) * ES);
+                v[s] = buf_load<CP_LOAD1>(in, src, lane, (uint32_t(slot_off<N, E, R0>(s)) << a.log2p) * ES);
+        } else if constexpr (KIND == K_AXIS) {
+            const rsrc_t src = make_rsrc(in + base(line0 >> a.ax_log2L), uint32_t(a.n) * ES);
+            const uint32_t lane = axis_lane(line0, a.ax_in);
+#pragma unroll
+            for (int s = 0; s < E; ++s)
+                v[s] = buf_load(in, src, lane, (uint32_t(slot_off<N, E, R0>(s)) << a.ax_in[2]) * ES);
         } else {
             // Scratch layout S[j1/T1][k2][j1%T1]; the plan keeps T1 | TPL, so
             // j1 = j + off(s) with off(s) a multiple of T1.
@@ -213,7 +243,7 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
                 ((uint32_t(j >> l2T1) << (a.log2q + l2T1)) + uint32_t(j & (T1 - 1)) + (uint32_t(c) << l2T1)) * ES;
 #pragma unroll
             for (int s = 0; s < E; ++s)
-                v[s] = buf_load(in, src, lane, (uint32_t(slot_off<N, E, R0>(s)) << a.log2q) * ES);
+                v[s] = buf_load<CP_LOAD2>(in, src, lane, (uint32_t(slot_off<N, E, R0>(s)) << a.log2q) * ES);
         }
     }
 
@@ -238,7 +268,29 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
         return (j10 + cc) * ((s / RL) * TPL + (s % RL) * (N / RL));
     }
     __device__ __forceinline__ C weights(int64_t line0, C *ep) const {
-        if constexpr (KIND != K_PASS1) {
+        if constexpr (KIND == K_AXIS) {
+            // w_n^(u(c) (k0 + m k)) with k = j + off(s): A = w_n^(u(c) (k0 + m j))
+            // per thread, P[c][s] = w_n^(u(c) m off(s)) per line; exponents
+            // reduced mod n (a power of two) by unsigned wrap-around.
+            if (!a.ax_tw) return mk<C>(Real(1), Real(0));
+            const C *__restrict__ hi = static_cast<const C *>(a.tw_hi);
+            const C *__restrict__ lo = static_cast<const C *>(a.tw_lo);
+            const uint32_t lomask = (1u << a.log2h) - 1, nmask = uint32_t(a.n - 1);
+            const uint32_t l = uint32_t(line0 & ((int64_t(1) << a.ax_log2L) - 1));
+            const uint32_t lm = l & ((1u << a.ax_log2U) - 1), ld = l >> a.ax_log2U;
+            const bool per_line = a.ax_tw == 2;
+            const uint32_t u0 = per_line ? lm : ld << a.ax_log2U, k0 = per_line ? ld : 0u;
+            const uint32_t xa = ((u0 + (per_line ? uint32_t(c) : 0u)) * (k0 + (uint32_t(j) << a.ax_log2m))) & nmask;
+            const C A = cmul(hi[xa >> a.log2h], lo[xa & lomask]);
+            for (int i = tid; i < T * (E + 1); i += nthr) {
+                const int cc = i / (E + 1), s = i - cc * (E + 1);
+                if (s >= E) continue;
+                const uint32_t off = uint32_t(slot_off<N, E, RL>(s));
+                const uint32_t x = ((u0 + (per_line ? uint32_t(cc) : 0u)) * (off << a.ax_log2m)) & nmask;
+                ep[i] = cmul(hi[x >> a.log2h], lo[x & lomask]);
+            }
+            return A;
+        } else if constexpr (KIND != K_PASS1) {
             return mk<C>(Real(1), Real(0));
         } else {
             const C *__restrict__ hi = static_cast<const C *>(a.tw_hi);
@@ -261,7 +313,7 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
     // tile's pass-1 weights.
     __device__ __forceinline__ void transform_store(int64_t line0, C *v, const C *ep, C A) const {
         const bool active = line0 + c < a.lines;
-        if constexpr (KIND == K_PASS1 && !TILE) __syncthreads();
+        if constexpr ((KIND == K_PASS1 || KIND == K_AXIS) && !TILE) __syncthreads();
 
         if constexpr (PREC == PREC_FP32) run_stages<C, N, RMAX, E, SPLIT>(v, line, twl, j);
         else mfma_stages<PREC, N>(v, tile, a.pitch, twl, c, j, tid, F);
@@ -292,14 +344,28 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
             const C *P = ep + c * (E + 1);
 #pragma unroll
             for (int s = 0; s < E; ++s)
-                buf_store(cmulc(v[s], cmul(A, P[s])), dst, lane, (uint32_t(slot_off<N, E, RL>(s)) << lW) * ES);
+                buf_store<CP_STORE1>(cmulc(v[s], cmul(A, P[s])), dst, lane, (uint32_t(slot_off<N, E, RL>(s)) << lW) * ES);
+        } else if constexpr (KIND == K_AXIS) {
+            const rsrc_t dst = make_rsrc(out + base(line0 >> a.ax_log2L), uint32_t(a.n) * ES);
+            const uint32_t lane = axis_lane(line0, a.ax_out);
+            if (a.ax_tw) {
+                const C *P = ep + c * (E + 1);
+#pragma unroll
+                for (int s = 0; s < E; ++s)
+                    buf_store(cmulc(v[s], cmul(A, P[s])), dst, lane,
+                              (uint32_t(slot_off<N, E, RL>(s)) << a.ax_out[2]) * ES);
+            } else {
+#pragma unroll
+                for (int s = 0; s < E; ++s)
+                    buf_store(scale_im(v[s], sout), dst, lane, (uint32_t(slot_off<N, E, RL>(s)) << a.ax_out[2]) * ES);
+            }
         } else {
             const int64_t b = line0 >> a.log2q, k20 = line0 & qmask;
             const rsrc_t dst = make_rsrc(out + base(b) + k20, uint32_t(a.n - k20) * ES);
             const uint32_t lane = (uint32_t(c) + (uint32_t(j) << a.log2q)) * ES;
 #pragma unroll
             for (int s = 0; s < E; ++s)
-                buf_store(scale_im(v[s], sout), dst, lane, (uint32_t(slot_off<N, E, RL>(s)) << a.log2q) * ES);
+                buf_store<CP_STORE2>(scale_im(v[s], sout), dst, lane, (uint32_t(slot_off<N, E, RL>(s)) << a.log2q) * ES);
         }
     }
 
@@ -591,6 +657,11 @@ KernelFn pick(int log2N) {
     return row[log2N];
 }
 
+// Axis passes of the three-level lift: radix 16, lines of 2^5..2^11 (every
+// pass has at least two stages, so its weight table is published by a stage
+// barrier).
+constexpr int AXIS_LMIN = 5, AXIS_LMAX = 11;
+
 template <typename Real> KernelFn pick_default(int kind, int log2N, int rmax) {
     switch (kind * 100 + rmax) {
     case K_SINGLE * 100 + 16: return pick<Real, K_SINGLE, 16>(log2N);
@@ -599,6 +670,7 @@ template <typename Real> KernelFn pick_default(int kind, int log2N, int rmax) {
     case K_PASS1 * 100 + 2: return pick<Real, K_PASS1, 2>(log2N);
     case K_PASS2 * 100 + 16: return pick<Real, K_PASS2, 16>(log2N);
     case K_PASS2 * 100 + 2: return pick<Real, K_PASS2, 2>(log2N);
+    case K_AXIS * 100 + 16: return pick<Real, K_AXIS, 16, 0, AXIS_LMIN, AXIS_LMAX>(log2N);
     default: return nullptr;
     }
 }
@@ -640,6 +712,10 @@ template <int PREC> KernelFn pick_mfma_kind(int kind, int log2N) {
 }
 
 KernelFn pick_kernel(int dtype, int kind, int log2N, int rmax, const Variant &v) {
+    if (kind == K_AXIS && !v.is_default()) { // the split exchange (complex64) only
+        if (dtype != FFT_C64 || rmax != 16 || v.code() != 2) return nullptr;
+        return pick<float, K_AXIS, 16, 2, AXIS_LMIN, AXIS_LMAX>(log2N);
+    }
     if (v.prec) {
         if (dtype != FFT_C64 || rmax != 16 || v.emax != 16 || v.split || v.persist || v.dense) return nullptr;
         return v.prec == PREC_F16X2 ? pick_mfma_kind<PREC_F16X2>(kind, log2N)
@@ -689,7 +765,9 @@ struct fft_plan {
     void *tables = nullptr;
     size_t table_bytes = 0;
     const void *tw1 = nullptr, *tw2 = nullptr, *tw_hi = nullptr, *tw_lo = nullptr;
-    Launch k1, k2;
+    Launch k1, k2, k3; // k3: third pass of a three-level lift
+    int log2n1 = 0, log2n2 = 0, log2n3 = 0; // three-level lift n = n1 n2 n3 (n1 contiguous)
+    const void *tw3 = nullptr;
     Variant base1, base2; // the variants chosen at creation (precision FP32)
     int log2W = 0;        // scratch slab width (two-pass plans)
     bool no_remap = false;
@@ -723,13 +801,13 @@ struct fft_plan {
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;
-    // Benchmark timing: a ring of event triples (before pass 1, after pass 1,
-    // after pass 2) recorded on the execute stream; drained on read.
+    // Benchmark timing: a ring of event quadruples (before the first pass,
+    // after each pass) recorded on the execute stream; drained on read.
     bool timing = false;
     std::vector<hipEvent_t> ev;
     int ring_head = 0, ring_count = 0;
-    double ms[2] = {0, 0};
-    int64_t launches[2] = {0, 0};
+    double ms[3] = {0, 0, 0};
+    int64_t launches[3] = {0, 0, 0};
 };
 
 namespace {
@@ -744,7 +822,7 @@ TileShape tile_shape(int log2N, int rmax, size_t esize, int log2T, const Variant
     const int lsize = int(v.split ? esize / 2 : esize);
     TileShape ts;
     ts.pitch = exchange_pitch(N, T, N / E, lsize, kind != K_SINGLE);
-    ts.lds = lds_bytes(N, rmax, T, E, ts.pitch, lsize, int(esize), kind == K_PASS1, v.prec != 0);
+    ts.lds = lds_bytes(N, rmax, T, E, ts.pitch, lsize, int(esize), kind == K_PASS1 || kind == K_AXIS, v.prec != 0);
     return ts;
 }
 
@@ -831,6 +909,9 @@ bool plan_pass(Launch &L, int dtype, int kind, int log2N, int rmax, int64_t line
     if (want_T) {
         l2T = ilog2_exact(want_T);
         if (want_T > lines_per_transform || (cap1 && want_T > cap1)) return false;
+    } else if (kind == K_AXIS) { // rows of at least 128 contiguous bytes, 256 threads
+        l2T = choose_log2T(log2N, rmax, esize, lines_per_transform, 256, int(128 / esize), 0, kind, v);
+        if ((int64_t(1) << l2T) * int64_t(esize) < 128) return false;
     } else {
         const bool p1 = kind == K_PASS1;
         l2T = choose_log2T(log2N, rmax, esize, lines_per_transform, 512, p1 ? 2 : 4, p1 ? cap1 : 0, kind, v);
@@ -850,21 +931,26 @@ int gen_table(int dtype, void *dst, int64_t count, int64_t mult, int log2N) {
     return hipGetLastError() == hipSuccess ? FFT_OK : FFT_E_HIP;
 }
 
-constexpr int TIMING_RING = 1024;
+// Whether a plan without level options lifts to three levels.
+bool default_three_level(int t, int dtype, int radix, const Variant &v) {
+    (void)t;
+    (void)dtype;
+    (void)radix;
+    (void)v;
+    return false;
+}
+
+constexpr int TIMING_RING = 1024, RING_EVENTS = 4;
 
 // Accumulate the durations recorded in ring slot `slot` (waits for them).
 int drain_slot(fft_plan *p, int slot) {
-    hipEvent_t *e = &p->ev[size_t(slot) * 3];
-    const hipEvent_t last = p->passes == 1 ? e[1] : e[2];
-    if (hipEventSynchronize(last) != hipSuccess) return FFT_E_HIP;
-    float t = 0;
-    if (hipEventElapsedTime(&t, e[0], e[1]) != hipSuccess) return FFT_E_HIP;
-    p->ms[0] += t;
-    p->launches[0] += 1;
-    if (p->passes == 2) {
-        if (hipEventElapsedTime(&t, e[1], e[2]) != hipSuccess) return FFT_E_HIP;
-        p->ms[1] += t;
-        p->launches[1] += 1;
+    hipEvent_t *e = &p->ev[size_t(slot) * RING_EVENTS];
+    if (hipEventSynchronize(e[p->passes]) != hipSuccess) return FFT_E_HIP;
+    for (int k = 0; k < p->passes; ++k) {
+        float t = 0;
+        if (hipEventElapsedTime(&t, e[k], e[k + 1]) != hipSuccess) return FFT_E_HIP;
+        p->ms[k] += t;
+        p->launches[k] += 1;
     }
     return FFT_OK;
 }
@@ -1038,8 +1124,13 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
     if (o.lines_per_block < 0 || (o.lines_per_block & (o.lines_per_block - 1))) return FFT_E_ARG;
     if (o.lines_per_block2 < 0 || (o.lines_per_block2 & (o.lines_per_block2 - 1))) return FFT_E_ARG;
     constexpr int32_t known_flags = FFT_OPT_NO_XCD_REMAP | FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE |
-                                    FFT_OPT_PERSISTENT | FFT_OPT_ONE_TILE | FFT_OPT_DENSE;
+                                    FFT_OPT_PERSISTENT | FFT_OPT_ONE_TILE | FFT_OPT_DENSE |
+                                    FFT_OPT_TWO_LEVEL | FFT_OPT_THREE_LEVEL;
     if (o.flags & ~known_flags) return FFT_E_ARG;
+    if ((o.flags & FFT_OPT_TWO_LEVEL) && (o.flags & FFT_OPT_THREE_LEVEL)) return FFT_E_ARG;
+    if ((o.flags & FFT_OPT_THREE_LEVEL) && (o.log2_p || o.lines_per_block2 || o.values_per_thread2 ||
+                                             o.scratch_width))
+        return FFT_E_ARG; // two-level options
     if ((o.flags & FFT_OPT_SPLIT_EXCHANGE) && (o.flags & FFT_OPT_FULL_EXCHANGE)) return FFT_E_ARG;
     if ((o.flags & FFT_OPT_PERSISTENT) && (o.flags & FFT_OPT_ONE_TILE)) return FFT_E_ARG;
     if (o.values_per_thread != 0 && o.values_per_thread != 16 && o.values_per_thread != 32)
@@ -1073,7 +1164,32 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
     }
 
     const int mline = max_line(dtype);
-    if (o.log2_p == 0 && t <= mline) {
+    const bool three = (o.flags & FFT_OPT_THREE_LEVEL) ||
+                       (!(o.flags & FFT_OPT_TWO_LEVEL) && !o.log2_p && !o.lines_per_block2 && !o.scratch_width &&
+                        !o.values_per_thread2 && default_three_level(t, dtype, radix, var));
+    if (three) {
+        // n = n1 n2 n3: n1 the contiguous rows of the last pass, n3 the
+        // slowest axis (first pass); near-equal factors, n3 >= n1 >= n2.
+        p->passes = 3;
+        p->log2n3 = (t + 2) / 3;
+        p->log2n1 = (t - p->log2n3 + 1) / 2;
+        p->log2n2 = t - p->log2n3 - p->log2n1;
+        const int l1 = p->log2n1, l2 = p->log2n2, l3 = p->log2n3;
+        if (radix != 16 || l2 < AXIS_LMIN || l3 > AXIS_LMAX) {
+            free_plan(p);
+            return FFT_E_UNSUPPORTED;
+        }
+        const int want = o.lines_per_block;
+        if (!plan_pass(p->k1, dtype, K_AXIS, l3, radix, int64_t(1) << l1, batch << (l1 + l2), want, 0, var,
+                       p->device) ||
+            !plan_pass(p->k2, dtype, K_AXIS, l2, radix, int64_t(1) << l1, batch << (l1 + l3), want, 0, var,
+                       p->device) ||
+            !plan_pass(p->k3, dtype, K_AXIS, l1, radix, int64_t(1) << l3, batch << (l2 + l3), want, 0, var,
+                       p->device)) {
+            free_plan(p);
+            return FFT_E_UNSUPPORTED;
+        }
+    } else if (o.log2_p == 0 && t <= mline) {
         p->passes = 1;
         p->log2q = t;
         if (forced) { // the other variants are pass kernels only
@@ -1124,22 +1240,25 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
         }
         p->log2W = o.scratch_width ? ilog2_exact(o.scratch_width) : p->k1.log2T;
     }
-    if (o.flags & FFT_OPT_NO_XCD_REMAP) p->k1.remap = p->k2.remap = false;
+    if (o.flags & FFT_OPT_NO_XCD_REMAP) p->k1.remap = p->k2.remap = p->k3.remap = false;
     p->no_remap = (o.flags & FFT_OPT_NO_XCD_REMAP) != 0;
     p->base1 = p->k1.var;
     p->base2 = p->k2.var;
-    if (!p->k1.fn || (p->passes == 2 && !p->k2.fn)) {
+    if (!p->k1.fn || (p->passes >= 2 && !p->k2.fn) || (p->passes == 3 && !p->k3.fn)) {
         free_plan(p);
         return FFT_E_UNSUPPORTED;
     }
 
-    // Device memory: scratch (two-pass only) and the weight tables.
-    p->log2h = p->passes == 2 ? (t + 1) / 2 : 0;
-    const int64_t n1 = int64_t(1) << p->log2q;                          // pass-1 line
-    const int64_t n2 = p->passes == 2 ? (int64_t(1) << p->log2p) : 0;   // pass-2 line
-    const int64_t nhi = p->passes == 2 ? (n >> p->log2h) : 0;
-    const int64_t nlo = p->passes == 2 ? (int64_t(1) << p->log2h) : 0;
-    const int64_t entries = n1 + n2 + nhi + nlo;
+    // Device memory: scratch (lifted plans only) and the weight tables: one
+    // w_N table per pass (N its line length) and the two-level w_n table.
+    const bool lifted = p->passes >= 2;
+    p->log2h = lifted ? (t + 1) / 2 : 0;
+    const int64_t n1 = int64_t(1) << p->k1.log2N; // first pass's line
+    const int64_t n2 = lifted ? (int64_t(1) << p->k2.log2N) : 0;
+    const int64_t n3 = p->passes == 3 ? (int64_t(1) << p->k3.log2N) : 0;
+    const int64_t nhi = lifted ? (n >> p->log2h) : 0;
+    const int64_t nlo = lifted ? (int64_t(1) << p->log2h) : 0;
+    const int64_t entries = n1 + n2 + n3 + nhi + nlo;
     p->table_bytes = size_t(entries) * esize;
     if (hipMalloc(&p->tables, p->table_bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -1147,7 +1266,7 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
         free_plan(p);
         return FFT_E_OOM;
     }
-    if (p->passes == 2) {
+    if (lifted) {
         p->scratch_bytes = size_t(n) * size_t(batch) * esize;
         if (hipMalloc(&p->scratch, p->scratch_bytes) != hipSuccess) {
             (void)hipGetLastError();
@@ -1158,13 +1277,15 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
     }
     char *tb = static_cast<char *>(p->tables);
     p->tw1 = tb;
-    int rc = gen_table(dtype, tb, n1, 1, p->log2q);
-    if (p->passes == 2) {
-        char *t2 = tb + n1 * esize, *th = t2 + n2 * esize, *tl = th + nhi * esize;
+    int rc = gen_table(dtype, tb, n1, 1, p->k1.log2N);
+    if (lifted) {
+        char *t2 = tb + n1 * esize, *t3 = t2 + n2 * esize, *th = t3 + n3 * esize, *tl = th + nhi * esize;
         p->tw2 = t2;
+        p->tw3 = t3;
         p->tw_hi = th;
         p->tw_lo = tl;
-        if (rc == FFT_OK) rc = gen_table(dtype, t2, n2, 1, p->log2p);
+        if (rc == FFT_OK) rc = gen_table(dtype, t2, n2, 1, p->k2.log2N);
+        if (rc == FFT_OK && n3) rc = gen_table(dtype, t3, n3, 1, p->k3.log2N);
         if (rc == FFT_OK) rc = gen_table(dtype, th, nhi, nlo, t);
         if (rc == FFT_OK) rc = gen_table(dtype, tl, nlo, 1, t);
     }
@@ -1474,7 +1595,7 @@ int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void 
             rc = drain_slot(p, slot);
             --p->ring_count;
         }
-        ev = &p->ev[size_t(p->ring_head) * 3];
+        ev = &p->ev[size_t(p->ring_head) * RING_EVENTS];
         if (rc == FFT_OK && !p->ragged) rc = hipEventRecord(ev[0], st) == hipSuccess ? FFT_OK : FFT_E_HIP;
     }
     if (p->ragged) {
@@ -1491,6 +1612,41 @@ int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void 
         a.xcd_remap = p->k1.remap;
         if (rc == FFT_OK) rc = launch(p, p->k1, a, st);
         if (rc == FFT_OK && ev) rc = hipEventRecord(ev[1], st) == hipSuccess ? FFT_OK : FFT_E_HIP;
+    } else if (p->passes == 3) {
+        // x -> out (slowest axis, weights w_(n2 n3)), out -> scratch (middle
+        // axis, weights w_n), scratch -> out (contiguous rows, natural order).
+        const int l1 = p->log2n1, l2 = p->log2n2, l3 = p->log2n3;
+        const void *src[3] = {in, out, p->scratch};
+        void *dst[3] = {out, p->scratch, out};
+        const void *tw[3] = {p->tw1, p->tw2, p->tw3};
+        const Launch *K[3] = {&p->k1, &p->k2, &p->k3};
+        const int32_t U[3] = {l1, l1, l3}, Lt[3] = {l1 + l2, l1 + l3, l2 + l3};
+        const int32_t ins[3][3] = {{0, l1, l1 + l2}, {0, l1 + l2, l1}, {l1 + l2, l1, 0}};
+        const int32_t outs[3][3] = {{0, l1, l1 + l2}, {0, l1 + l2, l1}, {0, l3, l2 + l3}};
+        a.tw_hi = p->tw_hi;
+        a.tw_lo = p->tw_lo;
+        for (int k = 0; k < 3 && rc == FFT_OK; ++k) {
+            a.in = src[k];
+            a.out = dst[k];
+            a.tw = tw[k];
+            a.lines = K[k]->lines;
+            a.ntiles = K[k]->ntiles;
+            a.pitch = K[k]->pitch;
+            a.log2T = a.log2T1 = K[k]->log2T;
+            a.conj_in = k == 0 ? inv : 0;
+            a.conj_out = k == 2 ? inv : 0;
+            a.xcd_remap = K[k]->remap;
+            a.ax_log2U = U[k];
+            a.ax_log2L = Lt[k];
+            for (int d = 0; d < 3; ++d) {
+                a.ax_in[d] = ins[k][d];
+                a.ax_out[d] = outs[k][d];
+            }
+            a.ax_tw = k == 2 ? 0 : k + 1;
+            a.ax_log2m = k == 1 ? l3 : 0;
+            rc = launch(p, *K[k], a, st);
+            if (rc == FFT_OK && ev) rc = hipEventRecord(ev[k + 1], st) == hipSuccess ? FFT_OK : FFT_E_HIP;
+        }
     } else {
         a.in = in;
         a.out = p->scratch;
@@ -1557,6 +1713,22 @@ int fft_plan_get_info(const fft_plan *p, fft_plan_info *info) {
     info->variant_pass1 = p->k1.var.code();
     info->variant_pass2 = p->passes == 2 ? p->k2.var.code() : 0;
     info->precision = p->precision;
+    info->levels = p->ragged ? 0 : p->passes;
+    if (p->passes == 3 && !p->ragged) {
+        info->log2_p = info->log2_q = 0;
+        info->log2_n1 = p->log2n1;
+        info->log2_n2 = p->log2n2;
+        info->log2_n3 = p->log2n3;
+        info->lines_per_block_pass2 = 1 << p->k2.log2T;
+        info->grid_pass2 = int32_t(p->k2.grid);
+        info->threads_pass2 = p->k2.threads;
+        info->lds_bytes_pass2 = int64_t(p->k2.lds);
+        info->variant_pass2 = p->k2.var.code();
+        info->lines_per_block_pass3 = 1 << p->k3.log2T;
+        info->grid_pass3 = int32_t(p->k3.grid);
+        info->threads_pass3 = p->k3.threads;
+        info->lds_bytes_pass3 = int64_t(p->k3.lds);
+    }
     if (p->ragged) {
         info->lines_per_block_pass1 = info->lines_per_block_pass2 = 0;
         info->grid_pass1 = int32_t(p->ra.grid);
@@ -1575,7 +1747,7 @@ int fft_plan_get_info(const fft_plan *p, fft_plan_info *info) {
 int fft_plan_set_precision(fft_plan *p, int mode) {
     if (!p) return FFT_E_NULL;
     if (mode != FFT_PREC_FP32 && mode != FFT_PREC_F16X2 && mode != FFT_PREC_BF16X2) return FFT_E_ARG;
-    if (p->ragged) return mode == FFT_PREC_FP32 ? FFT_OK : FFT_E_UNSUPPORTED;
+    if (p->ragged || p->passes == 3) return mode == FFT_PREC_FP32 ? FFT_OK : FFT_E_UNSUPPORTED;
     Launch n1 = p->k1, n2 = p->k2;
     auto redo = [&](Launch &L, const Variant &base) {
         Variant v = base;
@@ -1597,7 +1769,7 @@ int fft_plan_set_precision(fft_plan *p, int mode) {
 int fft_plan_set_timing(fft_plan *p, int enable) {
     if (!p) return FFT_E_NULL;
     if (enable && p->ev.empty()) {
-        p->ev.assign(size_t(TIMING_RING) * 3, nullptr);
+        p->ev.assign(size_t(TIMING_RING) * RING_EVENTS, nullptr);
         for (auto &e : p->ev) {
             if (hipEventCreate(&e) != hipSuccess) {
                 (void)hipGetLastError();
@@ -1615,16 +1787,16 @@ int fft_plan_set_timing(fft_plan *p, int enable) {
     return FFT_OK;
 }
 
-int fft_plan_read_timing(fft_plan *p, double ms_out[2], int64_t launches_out[2], int reset) {
+int fft_plan_read_timing(fft_plan *p, double ms_out[3], int64_t launches_out[3], int reset) {
     if (!p || !ms_out || !launches_out) return FFT_E_NULL;
     const int rc = p->ev.empty() ? FFT_OK : drain_all(p);
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 3; ++k) {
         ms_out[k] = p->ms[k];
         launches_out[k] = p->launches[k];
-    }
-    if (reset) {
-        p->ms[0] = p->ms[1] = 0;
-        p->launches[0] = p->launches[1] = 0;
+        if (reset) {
+            p->ms[k] = 0;
+            p->launches[k] = 0;
+        }
     }
     return rc;
 }

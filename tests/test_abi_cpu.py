@@ -143,3 +143,31 @@ def test_create_tuned_validation():
     assert L.fft_plan_create_tuned(1024, 1, 0, 0, None, ctypes.byref(res)) == -4
     assert L.fft_plan_create_tuned(1024, 1, 0, -1, ctypes.byref(h), ctypes.byref(res)) == -9
     assert h.value is None
+
+
+def test_level_options_validation():
+    """Two- and three-level flags: contradictory or two-level-only options
+    with the three-level lift are refused before any device work."""
+    from paper_0811_2535_amd.binding import FFT_OPT_THREE_LEVEL, FFT_OPT_TWO_LEVEL, PlanOpts
+    L = _lib()
+    h = ctypes.c_void_p(123)
+    both = PlanOpts(0, 0, 0, 0, FFT_OPT_TWO_LEVEL | FFT_OPT_THREE_LEVEL)
+    assert L.fft_plan_create_ex(1 << 24, 1, 0, ctypes.byref(both), ctypes.byref(h)) == -9
+    assert h.value is None
+    for opts in (PlanOpts(8, 0, 0, 0, FFT_OPT_THREE_LEVEL), PlanOpts(0, 0, 0, 4, FFT_OPT_THREE_LEVEL),
+                 PlanOpts(0, 0, 0, 0, FFT_OPT_THREE_LEVEL, 0, 16), PlanOpts(0, 0, 0, 0, FFT_OPT_THREE_LEVEL, 0, 0, 4)):
+        assert L.fft_plan_create_ex(1 << 24, 1, 0, ctypes.byref(opts), ctypes.byref(h)) == -9
+    assert L.fft_plan_create_ex(1 << 24, 1, 0, ctypes.byref(PlanOpts(0, 0, 0, 0, 512)), ctypes.byref(h)) == -9
+
+
+def test_info_struct_matches_header():
+    """The binding's fft_plan_info mirrors the header's field list."""
+    from paper_0811_2535_amd.binding import PlanInfo
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct fft_plan_info {"):text.index("} fft_plan_info;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = []
+    for decl in re.findall(r"(?:int32_t|int64_t)\s+([^;]+);", body):
+        names += [v.strip() for v in decl.split(",")]
+    assert [f for f, _ in PlanInfo._fields_] == names
+
