@@ -71,8 +71,8 @@ enum {
 /*
  * Create a plan for `batch` transforms of length `n` of element type `dtype`.
  * Validates the arguments, chooses the lift (single pass when n fits one
- * workgroup, else p x q with q >= p, or the three-level lift where it is
- * the faster one), allocates the scratch array (n*batch elements, lifted
+ * workgroup, else p x q with q >= p, or from n = 2^24 on the three-level
+ * lift described below), allocates the scratch array (n*batch elements, lifted
  * plans only) and the twiddle tables, and fills the tables
  * on the current device with an FP64 kernel (each entry computed directly
  * from its integer exponent, rounded once to the element type).  Synchronous.
@@ -111,7 +111,10 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out);
  *                     thread, one tile per workgroup only).
  *                     FFT_OPT_TWO_LEVEL / FFT_OPT_THREE_LEVEL: force the
  *                     two-level lift p x q (two passes) / the three-level
- *                     lift (see below) instead of the library's choice.
+ *                     lift (see below) instead of the library's choice
+ *                     (three levels from n = 2^24 on, radix 16 and default
+ *                     kernels, unless a two-level option or lines_per_block
+ *                     is given).
  *                     FFT_OPT_THREE_LEVEL takes no two-level options
  *                     (log2_p, lines_per_block2, values_per_thread2,
  *                     scratch_width: FFT_E_ARG); lines_per_block then sets
@@ -265,7 +268,8 @@ int fft_plan_get_info(const fft_plan *plan, fft_plan_info *info);
  * a power of two.  This is a different arithmetic from the paper's radix-2
  * butterflies (same transform, larger rounding error: about 1e-6 relative
  * L2 for FP16 pairs, 1e-5 for BF16 pairs); tests state the measured error.
- * Available for complex64 plans whose pass lines are 16, 256 or 4096 points
+ * Available for complex64 single-pass and two-level plans (not three-level
+ * ones: create those with FFT_OPT_TWO_LEVEL from 2^24 on) whose pass lines are 16, 256 or 4096 points
  * (every stage radix 16) with radix 16, 16 values per thread and one tile
  * per workgroup; otherwise FFT_E_UNSUPPORTED and the plan is unchanged.
  * FFT_E_ARG for an unknown mode.  Takes effect for later executes.
@@ -288,9 +292,12 @@ int fft_plan_read_timing(fft_plan *plan, double ms_out[3], int64_t launches_out[
 
 /*
  * Autotuned plan: the default plan plus up to max_candidates - 1 other
- * configurations of the same transform (0 = 48) -- other lifts n = p*q and
- * the single/two-pass threshold, radix 2, the pass-kernel variants and tile
- * widths -- each timed on device buffers the call allocates (forward
+ * configurations of the same transform (0 = 48) -- three-level lifts
+ * (n >= 2^15; tile widths 16 and 32, complex or split exchange), the
+ * two-level default, other lifts n = p*q and the single/two-pass threshold,
+ * radix 2, the pass-kernel variants and tile widths, each naming its lift
+ * with FFT_OPT_TWO_LEVEL or FFT_OPT_THREE_LEVEL -- each timed on device
+ * buffers the call allocates (forward
  * executes on a private stream, about 2 ms of work each) and checked
  * against the default plan's output (a configuration whose output differs
  * by more than 1e-4 (complex64) or 1e-10 (complex128) of the largest output

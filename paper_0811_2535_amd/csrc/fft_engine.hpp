@@ -288,24 +288,32 @@ template <int N, int E, int R> __device__ __forceinline__ constexpr int slot_off
     return (s / R) * (N / E) + (s % R) * (N / R);
 }
 
-// Fill the stage twiddle tables in LDS from the global table w_N^e (e < N,
-// +1 root).  Every thread of the workgroup takes part; a barrier must follow
-// before the tables are read.
-template <typename C, int N, int RMAX, int STG = 1>
-__device__ __forceinline__ void fill_twiddles(C *twl, const C *__restrict__ tw, int tid, int nthr) {
-    if constexpr (STG < sched_nstages(N, RMAX)) {
+// Source of entry i of the LDS stage tables (stages 1.. laid out back to
+// back, rows of R+1 entries): the index e*(N/M) of w_M^e in the global table
+// w_N^e (e < N, +1 root), or -1 for a row's padding slot.  LO rows hold
+// w_M^(r*row), HI rows w_M^(16*r*(row-LO)).
+template <int N, int RMAX, int STG = 1> __device__ __forceinline__ int tw_source(int i) {
+    if constexpr (STG >= sched_nstages(N, RMAX)) {
+        return -1;
+    } else {
         constexpr int R = sched_radix(N, RMAX, STG), NS = sched_ns(N, RMAX, STG);
-        constexpr int M = NS * R, ROW = R + 1;
-        constexpr int LO = tw_lo_rows(N, RMAX, STG), HI = tw_hi_rows(N, RMAX, STG);
-        constexpr int OFF = tw_stage_off(N, RMAX, STG);
-        for (int i = tid; i < (LO + HI) * ROW; i += nthr) {
-            const int row = i / ROW, r = i - row * ROW;
-            if (r >= R) continue;
-            // LO rows: w_M^(r*row); HI rows: w_M^(16*r*(row-LO)).
-            const int ex = row < LO ? r * row : 16 * r * (row - LO);
-            twl[OFF + i] = tw[ex * (N / M)];
-        }
-        fill_twiddles<C, N, RMAX, STG + 1>(twl, tw, tid, nthr);
+        constexpr int M = NS * R, ROW = R + 1, LO = tw_lo_rows(N, RMAX, STG);
+        constexpr int SZ = tw_stage_size(N, RMAX, STG);
+        if (i >= SZ) return tw_source<N, RMAX, STG + 1>(i - SZ);
+        const int row = i / ROW, r = i - row * ROW;
+        if (r >= R) return -1;
+        return (row < LO ? r * row : 16 * r * (row - LO)) * (N / M);
+    }
+}
+
+// Fill the stage twiddle tables in LDS from the global table.  Every thread
+// of the workgroup takes part, from entry `first` on; a barrier must follow
+// before the tables are read.
+template <typename C, int N, int RMAX>
+__device__ __forceinline__ void fill_twiddles(C *twl, const C *__restrict__ tw, int tid, int nthr, int first = 0) {
+    for (int i = first + tid; i < tw_total(N, RMAX); i += nthr) {
+        const int g = tw_source<N, RMAX>(i);
+        if (g >= 0) twl[i] = tw[g];
     }
 }
 

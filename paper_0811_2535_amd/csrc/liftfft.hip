@@ -258,55 +258,113 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
         if constexpr (TILE) fill_twiddles<C, N, RMAX>(twl, static_cast<const C *>(a.tw), tid, nthr);
     }
 
-    // Pass 1: this tile's inter-pass weights.  w_n^(-j1*k2) with k2 = j +
-    // off(s) is w_n^(j1*j) (per thread, returned) times P[c][s] =
-    // w_n^(j1*off(s)) (per line, written to the LDS buffer `ep`), both from
-    // the two-level FP64-generated tables.  The LDS table is published by the
-    // first barrier of the stage loop (or the explicit one in transform_store
-    // when the schedule has one stage).
+    // Weights fused into the store of pass 1 and of the weighted axis passes:
+    // the factor of element (c, k = j + off(s)) is w_n^-(u(c) (k0 + m k)),
+    // split as A = w_n^(u(c) (k0 + m j)) (per thread) times P[c][s] =
+    // w_n^(u(c) m off(s)) (per line and slot, in the LDS buffer `ep`), each
+    // from the two-level FP64-generated tables.  Pass 1: u = j1 (the column),
+    // k0 = 0, m = 1.  Axis passes: as selected by ax_tw.  Exponents are
+    // reduced mod n (a power of two) by unsigned wrap-around.  The LDS table
+    // is published by the first barrier of the stage loop (or the explicit
+    // one in transform_store when the schedule has one stage).
+    static constexpr bool WEIGHTED = KIND == K_PASS1 || KIND == K_AXIS;
     __device__ __forceinline__ int weight_exponent(int j10, int cc, int s) const {
         return (j10 + cc) * ((s / RL) * TPL + (s % RL) * (N / RL));
     }
-    __device__ __forceinline__ C weights(int64_t line0, C *ep) const {
+    struct WeightTerms {
+        uint32_t u0, du, k0; // u(c) = u0 + du * c
+    };
+    __device__ __forceinline__ bool weighted() const { return KIND == K_PASS1 || (KIND == K_AXIS && a.ax_tw); }
+    __device__ __forceinline__ WeightTerms weight_terms(int64_t line0) const {
         if constexpr (KIND == K_AXIS) {
-            // w_n^(u(c) (k0 + m k)) with k = j + off(s): A = w_n^(u(c) (k0 + m j))
-            // per thread, P[c][s] = w_n^(u(c) m off(s)) per line; exponents
-            // reduced mod n (a power of two) by unsigned wrap-around.
-            if (!a.ax_tw) return mk<C>(Real(1), Real(0));
-            const C *__restrict__ hi = static_cast<const C *>(a.tw_hi);
-            const C *__restrict__ lo = static_cast<const C *>(a.tw_lo);
-            const uint32_t lomask = (1u << a.log2h) - 1, nmask = uint32_t(a.n - 1);
             const uint32_t l = uint32_t(line0 & ((int64_t(1) << a.ax_log2L) - 1));
             const uint32_t lm = l & ((1u << a.ax_log2U) - 1), ld = l >> a.ax_log2U;
-            const bool per_line = a.ax_tw == 2;
-            const uint32_t u0 = per_line ? lm : ld << a.ax_log2U, k0 = per_line ? ld : 0u;
-            const uint32_t xa = ((u0 + (per_line ? uint32_t(c) : 0u)) * (k0 + (uint32_t(j) << a.ax_log2m))) & nmask;
-            const C A = cmul(hi[xa >> a.log2h], lo[xa & lomask]);
-            for (int i = tid; i < T * (E + 1); i += nthr) {
-                const int cc = i / (E + 1), s = i - cc * (E + 1);
-                if (s >= E) continue;
-                const uint32_t off = uint32_t(slot_off<N, E, RL>(s));
-                const uint32_t x = ((u0 + (per_line ? uint32_t(cc) : 0u)) * (off << a.ax_log2m)) & nmask;
-                ep[i] = cmul(hi[x >> a.log2h], lo[x & lomask]);
-            }
-            return A;
-        } else if constexpr (KIND != K_PASS1) {
-            return mk<C>(Real(1), Real(0));
+            return a.ax_tw == 2 ? WeightTerms{lm, 1u, ld} : WeightTerms{ld << a.ax_log2U, 0u, 0u};
         } else {
+            return WeightTerms{uint32_t(line0 & pmask), 1u, 0u};
+        }
+    }
+    __device__ __forceinline__ uint32_t exponent_A(const WeightTerms &w) const {
+        const uint32_t m = KIND == K_AXIS ? uint32_t(a.ax_log2m) : 0u;
+        return ((w.u0 + w.du * uint32_t(c)) * (w.k0 + (uint32_t(j) << m))) & uint32_t(a.n - 1);
+    }
+    __device__ __forceinline__ uint32_t exponent_P(const WeightTerms &w, int cc, int s) const {
+        const uint32_t m = KIND == K_AXIS ? uint32_t(a.ax_log2m) : 0u;
+        return ((w.u0 + w.du * uint32_t(cc)) * (uint32_t(slot_off<N, E, RL>(s)) << m)) & uint32_t(a.n - 1);
+    }
+
+    // Table entries of one tile (stage twiddles, weights), loaded into
+    // registers before the tile's data and written to LDS after the data
+    // loads are issued: global loads complete in order, so a table entry
+    // loaded after the data (and consumed at once) would add its latency to
+    // the data's.  The loads are unconditional (unused slots read entry 0)
+    // so that the compiler's count of loads in flight stays exact.  Each
+    // thread stages at most two entries of each table; the rest, if any, are
+    // copied directly.
+    struct TableRegs {
+        C tw[2], ahi, alo, ehi[2], elo[2];
+    };
+    __device__ __forceinline__ void fetch_tables(int64_t line0, TableRegs &r) const {
+        const C *__restrict__ tw = static_cast<const C *>(a.tw);
+        if constexpr (TILE) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int i = tid + k * nthr, g = i < tw_total(N, RMAX) ? tw_source<N, RMAX>(i) : -1;
+                r.tw[k] = tw[g < 0 ? 0 : g];
+            }
+        }
+        if constexpr (WEIGHTED) {
             const C *__restrict__ hi = static_cast<const C *>(a.tw_hi);
             const C *__restrict__ lo = static_cast<const C *>(a.tw_lo);
-            const int lomask = (1 << a.log2h) - 1;
-            const int j10 = int(line0 & pmask);
-            const int xa = (j10 + c) * j;
-            const C A = cmul(hi[xa >> a.log2h], lo[xa & lomask]);
-            for (int i = tid; i < T * (E + 1); i += nthr) {
-                const int cc = i / (E + 1), s = i - cc * (E + 1);
-                if (s >= E) continue;
-                const int x = weight_exponent(j10, cc, s);
-                ep[i] = cmul(hi[x >> a.log2h], lo[x & lomask]);
+            const uint32_t lomask = (1u << a.log2h) - 1;
+            const WeightTerms w = weight_terms(line0);
+            const uint32_t xa = exponent_A(w);
+            r.ahi = hi[xa >> a.log2h];
+            r.alo = lo[xa & lomask];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int i = tid + k * nthr, cc = i / (E + 1), s = i - cc * (E + 1);
+                const uint32_t x = i < T * (E + 1) && s < E ? exponent_P(w, cc, s) : 0u;
+                r.ehi[k] = hi[x >> a.log2h];
+                r.elo[k] = lo[x & lomask];
             }
-            return A;
         }
+    }
+    // Write the staged entries (and any remaining ones) to LDS; returns A.
+    __device__ __forceinline__ C publish_tables(int64_t line0, const TableRegs &r, C *ep) const {
+        if constexpr (TILE) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int i = tid + k * nthr, g = i < tw_total(N, RMAX) ? tw_source<N, RMAX>(i) : -1;
+                if (g >= 0) twl[i] = r.tw[k];
+            }
+            if (2 * nthr < tw_total(N, RMAX))
+                fill_twiddles<C, N, RMAX>(twl, static_cast<const C *>(a.tw), tid, nthr, 2 * nthr);
+        }
+        C A = mk<C>(Real(1), Real(0));
+        if constexpr (WEIGHTED) {
+            if (weighted()) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int i = tid + k * nthr, cc = i / (E + 1), s = i - cc * (E + 1);
+                    if (i < T * (E + 1) && s < E) ep[i] = cmul(r.ehi[k], r.elo[k]);
+                }
+                if (2 * nthr < T * (E + 1)) {
+                    const C *__restrict__ hi = static_cast<const C *>(a.tw_hi);
+                    const C *__restrict__ lo = static_cast<const C *>(a.tw_lo);
+                    const uint32_t lomask = (1u << a.log2h) - 1;
+                    const WeightTerms w = weight_terms(line0);
+                    for (int i = tid + 2 * nthr; i < T * (E + 1); i += nthr) {
+                        const int cc = i / (E + 1), s = i - cc * (E + 1);
+                        if (s >= E) continue;
+                        const uint32_t x = exponent_P(w, cc, s);
+                        ep[i] = cmul(hi[x >> a.log2h], lo[x & lomask]);
+                    }
+                }
+                A = cmul(r.ahi, r.alo);
+            }
+        }
+        return A;
     }
 
     // Transform the tile held in v and store it; `ep` and `A` are this
@@ -373,10 +431,11 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
     // readers of the LDS).
     __device__ __forceinline__ void run_one(int64_t t) const {
         C v[E];
+        TableRegs r;
+        fetch_tables(t << log2T, r);
         load(t << log2T, v);
+        const C A = publish_tables(t << log2T, r, ep_base);
         conj_in(v);
-        fill_tw();
-        const C A = weights(t << log2T, ep_base);
         transform_store(t << log2T, v, ep_base, A);
     }
 };
@@ -931,13 +990,14 @@ int gen_table(int dtype, void *dst, int64_t count, int64_t mult, int log2N) {
     return hipGetLastError() == hipSuccess ? FFT_OK : FFT_E_HIP;
 }
 
-// Whether a plan without level options lifts to three levels.
+// Whether a plan without level or two-level options lifts to three
+// levels: from n = 2^24 on (both element types), where the three-level lift
+// measured faster on MI355X (2^24 complex64: 175 us against 197 us; 2^26:
+// 704 against 1199; 2^28: 3.35 ms against 6.65 ms); below that the two
+// passes of the two-level lift are at least as fast.
 bool default_three_level(int t, int dtype, int radix, const Variant &v) {
-    (void)t;
     (void)dtype;
-    (void)radix;
-    (void)v;
-    return false;
+    return t >= 24 && radix == 16 && v.is_default();
 }
 
 constexpr int TIMING_RING = 1024, RING_EVENTS = 4;
@@ -1165,8 +1225,8 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
 
     const int mline = max_line(dtype);
     const bool three = (o.flags & FFT_OPT_THREE_LEVEL) ||
-                       (!(o.flags & FFT_OPT_TWO_LEVEL) && !o.log2_p && !o.lines_per_block2 && !o.scratch_width &&
-                        !o.values_per_thread2 && default_three_level(t, dtype, radix, var));
+                       (!(o.flags & FFT_OPT_TWO_LEVEL) && !o.log2_p && !o.lines_per_block && !o.lines_per_block2 &&
+                        !o.scratch_width && !o.values_per_thread2 && default_three_level(t, dtype, radix, var));
     if (three) {
         // n = n1 n2 n3: n1 the contiguous rows of the last pass, n3 the
         // slowest axis (first pass); near-equal factors, n3 >= n1 >= n2.
@@ -1824,6 +1884,7 @@ std::map<TuneKey, fft_tune_result> tune_cache;
 // radix 2; then, for the default split, the kernel variants and tile widths.
 std::vector<fft_plan_opts> tune_candidates(int t, int dtype) {
     std::vector<fft_plan_opts> c;
+    // Every candidate after the library default names its lift explicitly.
     auto add = [&](int log2_p, int radix, int lpb, int lpb2, int flags, int vpt) {
         fft_plan_opts o;
         memset(&o, 0, sizeof(o));
@@ -1831,11 +1892,16 @@ std::vector<fft_plan_opts> tune_candidates(int t, int dtype) {
         o.radix = radix;
         o.lines_per_block = lpb;
         o.lines_per_block2 = lpb2;
-        o.flags = flags;
+        o.flags = c.empty() || (flags & FFT_OPT_THREE_LEVEL) ? flags : flags | FFT_OPT_TWO_LEVEL;
         o.values_per_thread = vpt;
         c.push_back(o);
     };
     add(0, 0, 0, 0, 0, 0);
+    if (t >= 15) // three-level lifts: tile widths 16 and 32, complex or split exchange
+        for (int lpb : {16, 32})
+            for (int f : {0, int(FFT_OPT_SPLIT_EXCHANGE)})
+                if (dtype == FFT_C64 || !f) add(0, 0, lpb, 0, FFT_OPT_THREE_LEVEL | f, 0);
+    add(0, 0, 0, 0, 0, 0); // the two-level default
     const int lq = (t + 1) / 2, lp = t - lq;
     for (int d : {1, -1, 2}) { // splits p = 2^(lp + d); q = 2^(t - lp - d)
         const int l2p = lp + d;

@@ -69,7 +69,7 @@ def test_longest_single_pass_lines(lf, torch, t, dtype):
 def test_full_oracle_beyond_2p24(lf, torch, t, dtype):
     n = 1 << t
     tdt = torch.complex64 if dtype == np.complex64 else torch.complex128
-    plan = lf.Plan(n, 1, tdt)
+    plan = lf.Plan(n, 1, tdt, flags=128)  # FFT_OPT_TWO_LEVEL (the default here is three levels)
     info = plan.info()
     assert info["passes"] == 2 and info["log2_q"] == (t + 1) // 2
     x_np = datagen.signals(n, 1, dtype, "normal", 700 + t)
@@ -87,8 +87,8 @@ def test_full_oracle_beyond_2p24(lf, torch, t, dtype):
 @pytest.mark.parametrize("t", [27, 28])
 def test_properties_at_two_level_limit(lf, torch, t):
     n = 1 << t
-    plan = lf.Plan(n, 1, torch.complex64)
-    assert plan.info()["log2_q"] == (t + 1) // 2
+    plan = lf.Plan(n, 1, torch.complex64, flags=128)  # FFT_OPT_TWO_LEVEL
+    assert plan.info()["passes"] == 2 and plan.info()["log2_q"] == (t + 1) // 2
     # pure tone x_j = w_n^(a j): the forward transform is n at bin a
     a = 123457 % n
     j = torch.arange(n, device="cuda", dtype=torch.int64)

@@ -38,7 +38,9 @@ def lf(torch):
 def run_prec(lf, x_np, sign, mode, **opts):
     import torch
     batch, n = x_np.shape
-    plan = lf.Plan(n, batch, torch.complex64, **opts)
+    # the precision forms run on single-pass and two-level plans (at 2^24 the
+    # library's default is the three-level lift)
+    plan = lf.Plan(n, batch, torch.complex64, **dict(dict(flags=128), **opts))
     plan.set_precision(mode)
     assert plan.info()["precision"] == {"fp32": 0, "f16x2": 1, "bf16x2": 2}[mode]
     x = to_dev(x_np)

@@ -219,3 +219,18 @@ def test_timing_precision_and_errors(lf, torch):
         with pytest.raises(lf.FFTError) as e:
             lf.Plan(1 << t, 1, torch.complex64, **dict(dict(flags=THREE), **opts))
         assert e.value.code == code, (t, opts)
+
+
+def test_default_lift_by_size(lf, torch):
+    """The library lifts to three levels from 2^24 on (both element types)
+    unless a two-level option is given, and to two levels below."""
+    cases = [(23, torch.complex64, {}, 2), (24, torch.complex64, {}, 3), (24, torch.complex128, {}, 3),
+             (24, torch.complex64, dict(flags=TWO), 2), (24, torch.complex64, dict(log2_p=12), 2),
+             (24, torch.complex64, dict(lines_per_block=2), 2), (24, torch.complex64, dict(flags=2), 2),
+             (24, torch.complex64, dict(radix=2), 2), (22, torch.complex64, dict(flags=THREE), 3)]
+    for t, dt, opts, levels in cases:
+        p = lf.Plan(1 << t, 1, dt, **opts)
+        info = p.info()
+        p.destroy()
+        assert info["levels"] == info["passes"] == levels, (t, dt, opts, info["levels"])
+
