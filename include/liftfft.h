@@ -64,9 +64,10 @@ enum {
 
 /* Largest supported log2(n) per element type: one workgroup transforms lines
  * of up to 2^14 complex64 / 2^13 complex128 points, so transforms up to that
- * length run in one pass and the two-level lift reaches 2^28 / 2^26. */
-#define FFT_MAX_LOG2N_C64 28
-#define FFT_MAX_LOG2N_C128 26
+ * length run in one pass and the two-level lift reaches 2^28 / 2^26; the
+ * three-level lift reaches 2^30 / 2^29 (8 GiB per buffer). */
+#define FFT_MAX_LOG2N_C64 30
+#define FFT_MAX_LOG2N_C128 29
 
 /*
  * Create a plan for `batch` transforms of length `n` of element type `dtype`.
@@ -143,7 +144,9 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out);
  * so every pass reads and writes runs of at least 128 bytes.  Factors:
  * log2 n3 = ceil(t/3), log2 n1 = ceil((t - log2 n3)/2), n2 the rest; each
  * between 2^5 and 2^11 (15 <= t), radix 16, default or split-exchange
- * kernels; otherwise FFT_E_UNSUPPORTED.
+ * kernels (default kernels only for transforms of 2^31 bytes or more,
+ * which are addressed in 64 bits); otherwise FFT_E_UNSUPPORTED.  Two-level
+ * plans stop at 2^28 complex64 / 2^26 complex128 (FFT_E_UNSUPPORTED above).
  */
 enum {
     FFT_OPT_NO_XCD_REMAP = 1,
@@ -322,7 +325,7 @@ int fft_plan_create_tuned(int64_t n, int64_t batch, int dtype, int32_t max_candi
                           fft_tune_result *result);
 
 /* ABI version of this header (major*100 + minor). */
-#define LIFTFFT_ABI_VERSION 108
+#define LIFTFFT_ABI_VERSION 109
 int fft_abi_version(void);
 
 #ifdef __cplusplus

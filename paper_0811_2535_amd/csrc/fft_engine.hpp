@@ -281,6 +281,15 @@ template <int AUX = 0> __device__ __forceinline__ void buf_store(double2 v, rsrc
     __asm__ volatile("" ::: "memory");
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v.y), r, voff + 8, soff, AUX);
 }
+// Plain global store of one element (transforms addressed in 64 bits);
+// complex128 as two 8-byte stores, for the reason given above.
+__device__ __forceinline__ void global_store(float2 *p, float2 v) { *p = v; }
+__device__ __forceinline__ void global_store(double2 *p, double2 v) {
+    double *q = reinterpret_cast<double *>(p);
+    q[0] = v.x;
+    __asm__ volatile("" ::: "memory");
+    q[1] = v.y;
+}
 // Element index held by register slot s on entry (first-stage layout) or on
 // exit (last-stage layout) relative to the thread's j: slot i*R + r <->
 // j + i*TPL + r*(N/R), TPL = N/E.

@@ -46,7 +46,7 @@ using namespace liftfft;
 
 namespace {
 
-enum Kind { K_SINGLE = 0, K_PASS1 = 1, K_PASS2 = 2, K_AXIS = 3 };
+enum Kind { K_SINGLE = 0, K_PASS1 = 1, K_PASS2 = 2, K_AXIS = 3, K_AXIS_WIDE = 4 };
 
 constexpr int MAX_LOG2_LINE = 14; // longest line one workgroup transforms (complex64)
 // Longest line per element type: 2^14 complex64 points (1024 threads of 16
@@ -74,7 +74,7 @@ struct PassArgs {
     int32_t pitch;  // exchange line pitch, in exchange elements
     const int64_t *offsets; // packed uneven batch: first element of each transform (else b*n)
     int64_t total;          // packed uneven batch: elements in the buffer
-    // Axis passes of a three-level lift (K_AXIS).  Line l of a transform is
+    // Axis passes of a three-level lift (K_AXIS, K_AXIS_WIDE).  Line l of a transform is
     // (lm, ld) = (l mod 2^ax_log2U, l div 2^ax_log2U); element i of the line
     // sits at (lm << ax_in[0]) + (ld << ax_in[1]) + (i << ax_in[2]) and
     // result k goes to the same form over ax_out.  ax_tw selects the fused
@@ -141,6 +141,10 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
     static constexpr int NST = sched_nstages(N, RMAX);
     static constexpr int R0 = sched_radix(N, RMAX, 0), RL = sched_radix(N, RMAX, NST - 1);
     static constexpr bool TILE = uses_tile(N, RMAX);
+    // Axis passes; the wide form addresses a transform of 2^31 bytes or more
+    // through 64-bit global pointers instead of 32-bit buffer offsets.
+    static constexpr bool AXIS = KIND == K_AXIS || KIND == K_AXIS_WIDE;
+    static constexpr bool WIDE = KIND == K_AXIS_WIDE;
 
     const PassArgs &a;
     int log2T, T, tid, nthr, c, j;
@@ -203,6 +207,12 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
         const uint32_t lm = l & ((1u << a.ax_log2U) - 1), ld = l >> a.ax_log2U;
         return (((lm + uint32_t(c)) << st[0]) + (ld << st[1]) + (uint32_t(j) << st[2])) * ES;
     }
+    // The same as an element offset in 64 bits (wide form).
+    __device__ __forceinline__ int64_t axis_elem(int64_t line0, const int32_t *st) const {
+        const int64_t l = line0 & ((int64_t(1) << a.ax_log2L) - 1);
+        const int64_t lm = l & ((int64_t(1) << a.ax_log2U) - 1), ld = l >> a.ax_log2U;
+        return ((lm + c) << st[0]) + (ld << st[1]) + (int64_t(j) << st[2]);
+    }
 
     // Data loads of the tile starting at line0: a buffer descriptor, one
     // 32-bit lane offset, and a uniform per-slot offset.  Raw values: the
@@ -227,6 +237,10 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
 #pragma unroll
             for (int s = 0; s < E; ++s)
                 v[s] = buf_load<CP_LOAD1>(in, src, lane, (uint32_t(slot_off<N, E, R0>(s)) << a.log2p) * ES);
+        } else if constexpr (WIDE) {
+            const C *src = in + base(line0 >> a.ax_log2L) + axis_elem(line0, a.ax_in);
+#pragma unroll
+            for (int s = 0; s < E; ++s) v[s] = src[int64_t(slot_off<N, E, R0>(s)) << a.ax_in[2]];
         } else if constexpr (KIND == K_AXIS) {
             const rsrc_t src = make_rsrc(in + base(line0 >> a.ax_log2L), uint32_t(a.n) * ES);
             const uint32_t lane = axis_lane(line0, a.ax_in);
@@ -267,16 +281,16 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
     // reduced mod n (a power of two) by unsigned wrap-around.  The LDS table
     // is published by the first barrier of the stage loop (or the explicit
     // one in transform_store when the schedule has one stage).
-    static constexpr bool WEIGHTED = KIND == K_PASS1 || KIND == K_AXIS;
+    static constexpr bool WEIGHTED = KIND == K_PASS1 || AXIS;
     __device__ __forceinline__ int weight_exponent(int j10, int cc, int s) const {
         return (j10 + cc) * ((s / RL) * TPL + (s % RL) * (N / RL));
     }
     struct WeightTerms {
         uint32_t u0, du, k0; // u(c) = u0 + du * c
     };
-    __device__ __forceinline__ bool weighted() const { return KIND == K_PASS1 || (KIND == K_AXIS && a.ax_tw); }
+    __device__ __forceinline__ bool weighted() const { return KIND == K_PASS1 || (AXIS && a.ax_tw); }
     __device__ __forceinline__ WeightTerms weight_terms(int64_t line0) const {
-        if constexpr (KIND == K_AXIS) {
+        if constexpr (AXIS) {
             const uint32_t l = uint32_t(line0 & ((int64_t(1) << a.ax_log2L) - 1));
             const uint32_t lm = l & ((1u << a.ax_log2U) - 1), ld = l >> a.ax_log2U;
             return a.ax_tw == 2 ? WeightTerms{lm, 1u, ld} : WeightTerms{ld << a.ax_log2U, 0u, 0u};
@@ -285,11 +299,11 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
         }
     }
     __device__ __forceinline__ uint32_t exponent_A(const WeightTerms &w) const {
-        const uint32_t m = KIND == K_AXIS ? uint32_t(a.ax_log2m) : 0u;
+        const uint32_t m = AXIS ? uint32_t(a.ax_log2m) : 0u;
         return ((w.u0 + w.du * uint32_t(c)) * (w.k0 + (uint32_t(j) << m))) & uint32_t(a.n - 1);
     }
     __device__ __forceinline__ uint32_t exponent_P(const WeightTerms &w, int cc, int s) const {
-        const uint32_t m = KIND == K_AXIS ? uint32_t(a.ax_log2m) : 0u;
+        const uint32_t m = AXIS ? uint32_t(a.ax_log2m) : 0u;
         return ((w.u0 + w.du * uint32_t(cc)) * (uint32_t(slot_off<N, E, RL>(s)) << m)) & uint32_t(a.n - 1);
     }
 
@@ -302,16 +316,24 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
     // thread stages at most two entries of each table; the rest, if any, are
     // copied directly.
     struct TableRegs {
-        C tw[2], ahi, alo, ehi[2], elo[2];
+        C tw0, tw1, ahi, alo, ehi0, elo0, ehi1, elo1; // scalars: kept in registers
     };
+    __device__ __forceinline__ int tw_slot(int k) const {
+        const int i = tid + k * nthr;
+        return i < tw_total(N, RMAX) ? tw_source<N, RMAX>(i) : -1;
+    }
+    __device__ __forceinline__ bool ep_slot(int k, int &cc, int &s) const {
+        const int i = tid + k * nthr;
+        cc = i / (E + 1);
+        s = i - cc * (E + 1);
+        return i < T * (E + 1) && s < E;
+    }
     __device__ __forceinline__ void fetch_tables(int64_t line0, TableRegs &r) const {
-        const C *__restrict__ tw = static_cast<const C *>(a.tw);
         if constexpr (TILE) {
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int i = tid + k * nthr, g = i < tw_total(N, RMAX) ? tw_source<N, RMAX>(i) : -1;
-                r.tw[k] = tw[g < 0 ? 0 : g];
-            }
+            const C *__restrict__ tw = static_cast<const C *>(a.tw);
+            const int g0 = tw_slot(0), g1 = tw_slot(1);
+            r.tw0 = tw[g0 < 0 ? 0 : g0];
+            r.tw1 = tw[g1 < 0 ? 0 : g1];
         }
         if constexpr (WEIGHTED) {
             const C *__restrict__ hi = static_cast<const C *>(a.tw_hi);
@@ -321,43 +343,63 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
             const uint32_t xa = exponent_A(w);
             r.ahi = hi[xa >> a.log2h];
             r.alo = lo[xa & lomask];
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int i = tid + k * nthr, cc = i / (E + 1), s = i - cc * (E + 1);
-                const uint32_t x = i < T * (E + 1) && s < E ? exponent_P(w, cc, s) : 0u;
-                r.ehi[k] = hi[x >> a.log2h];
-                r.elo[k] = lo[x & lomask];
+            int cc, s;
+            const uint32_t x0 = ep_slot(0, cc, s) ? exponent_P(w, cc, s) : 0u;
+            const uint32_t x1 = ep_slot(1, cc, s) ? exponent_P(w, cc, s) : 0u;
+            r.ehi0 = hi[x0 >> a.log2h];
+            r.elo0 = lo[x0 & lomask];
+            r.ehi1 = hi[x1 >> a.log2h];
+            r.elo1 = lo[x1 & lomask];
+        }
+    }
+    // The same tables without staging, in the order the data arrives (for
+    // kernels without registers to spare: complex128 tiles and the uneven-
+    // batch kernel); returns A.
+    __device__ __forceinline__ C direct_tables(int64_t line0, C *ep) const {
+        if constexpr (TILE) fill_twiddles<C, N, RMAX>(twl, static_cast<const C *>(a.tw), tid, nthr);
+        C A = mk<C>(Real(1), Real(0));
+        if constexpr (WEIGHTED) {
+            if (weighted()) {
+                const C *__restrict__ hi = static_cast<const C *>(a.tw_hi);
+                const C *__restrict__ lo = static_cast<const C *>(a.tw_lo);
+                const uint32_t lomask = (1u << a.log2h) - 1;
+                const WeightTerms w = weight_terms(line0);
+                const uint32_t xa = exponent_A(w);
+                A = cmul(hi[xa >> a.log2h], lo[xa & lomask]);
+                for (int i = tid; i < T * (E + 1); i += nthr) {
+                    const int c2 = i / (E + 1), s2 = i - c2 * (E + 1);
+                    if (s2 >= E) continue;
+                    const uint32_t x = exponent_P(w, c2, s2);
+                    ep[i] = cmul(hi[x >> a.log2h], lo[x & lomask]);
+                }
             }
         }
+        return A;
     }
     // Write the staged entries (and any remaining ones) to LDS; returns A.
     __device__ __forceinline__ C publish_tables(int64_t line0, const TableRegs &r, C *ep) const {
         if constexpr (TILE) {
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int i = tid + k * nthr, g = i < tw_total(N, RMAX) ? tw_source<N, RMAX>(i) : -1;
-                if (g >= 0) twl[i] = r.tw[k];
-            }
+            const int g0 = tw_slot(0), g1 = tw_slot(1);
+            if (g0 >= 0) twl[tid] = r.tw0;
+            if (g1 >= 0) twl[tid + nthr] = r.tw1;
             if (2 * nthr < tw_total(N, RMAX))
                 fill_twiddles<C, N, RMAX>(twl, static_cast<const C *>(a.tw), tid, nthr, 2 * nthr);
         }
         C A = mk<C>(Real(1), Real(0));
         if constexpr (WEIGHTED) {
             if (weighted()) {
-#pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    const int i = tid + k * nthr, cc = i / (E + 1), s = i - cc * (E + 1);
-                    if (i < T * (E + 1) && s < E) ep[i] = cmul(r.ehi[k], r.elo[k]);
-                }
+                int cc, s;
+                if (ep_slot(0, cc, s)) ep[tid] = cmul(r.ehi0, r.elo0);
+                if (ep_slot(1, cc, s)) ep[tid + nthr] = cmul(r.ehi1, r.elo1);
                 if (2 * nthr < T * (E + 1)) {
                     const C *__restrict__ hi = static_cast<const C *>(a.tw_hi);
                     const C *__restrict__ lo = static_cast<const C *>(a.tw_lo);
                     const uint32_t lomask = (1u << a.log2h) - 1;
                     const WeightTerms w = weight_terms(line0);
                     for (int i = tid + 2 * nthr; i < T * (E + 1); i += nthr) {
-                        const int cc = i / (E + 1), s = i - cc * (E + 1);
-                        if (s >= E) continue;
-                        const uint32_t x = exponent_P(w, cc, s);
+                        const int c2 = i / (E + 1), s2 = i - c2 * (E + 1);
+                        if (s2 >= E) continue;
+                        const uint32_t x = exponent_P(w, c2, s2);
                         ep[i] = cmul(hi[x >> a.log2h], lo[x & lomask]);
                     }
                 }
@@ -371,7 +413,7 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
     // tile's pass-1 weights.
     __device__ __forceinline__ void transform_store(int64_t line0, C *v, const C *ep, C A) const {
         const bool active = line0 + c < a.lines;
-        if constexpr ((KIND == K_PASS1 || KIND == K_AXIS) && !TILE) __syncthreads();
+        if constexpr ((KIND == K_PASS1 || AXIS) && !TILE) __syncthreads();
 
         if constexpr (PREC == PREC_FP32) run_stages<C, N, RMAX, E, SPLIT>(v, line, twl, j);
         else mfma_stages<PREC, N>(v, tile, a.pitch, twl, c, j, tid, F);
@@ -403,6 +445,18 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
 #pragma unroll
             for (int s = 0; s < E; ++s)
                 buf_store<CP_STORE1>(cmulc(v[s], cmul(A, P[s])), dst, lane, (uint32_t(slot_off<N, E, RL>(s)) << lW) * ES);
+        } else if constexpr (WIDE) {
+            C *dst = out + base(line0 >> a.ax_log2L) + axis_elem(line0, a.ax_out);
+            if (a.ax_tw) {
+                const C *P = ep + c * (E + 1);
+#pragma unroll
+                for (int s = 0; s < E; ++s)
+                    global_store(dst + (int64_t(slot_off<N, E, RL>(s)) << a.ax_out[2]), cmulc(v[s], cmul(A, P[s])));
+            } else {
+#pragma unroll
+                for (int s = 0; s < E; ++s)
+                    global_store(dst + (int64_t(slot_off<N, E, RL>(s)) << a.ax_out[2]), scale_im(v[s], sout));
+            }
         } else if constexpr (KIND == K_AXIS) {
             const rsrc_t dst = make_rsrc(out + base(line0 >> a.ax_log2L), uint32_t(a.n) * ES);
             const uint32_t lane = axis_lane(line0, a.ax_out);
@@ -429,13 +483,24 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
 
     // One tile, start to finish (the caller orders it after any earlier
     // readers of the LDS).
-    __device__ __forceinline__ void run_one(int64_t t) const {
+    // STAGE: table entries staged in registers ahead of the data (complex64
+    // pass kernels with 16 values per thread); else loaded after it (kernels
+    // whose staged entries would be spilled to scratch memory: complex128
+    // tiles, 32 values per thread, the 64-VGPR cap, the uneven-batch kernel).
+    template <bool STAGE> __device__ __forceinline__ void run_one(int64_t t) const {
         C v[E];
-        TableRegs r;
-        fetch_tables(t << log2T, r);
-        load(t << log2T, v);
-        const C A = publish_tables(t << log2T, r, ep_base);
-        conj_in(v);
+        C A;
+        if constexpr (STAGE) {
+            TableRegs r;
+            fetch_tables(t << log2T, r);
+            load(t << log2T, v);
+            A = publish_tables(t << log2T, r, ep_base);
+            conj_in(v);
+        } else {
+            load(t << log2T, v);
+            conj_in(v);
+            A = direct_tables(t << log2T, ep_base);
+        }
         transform_store(t << log2T, v, ep_base, A);
     }
 };
@@ -458,7 +523,8 @@ __global__ __launch_bounds__((max_threads<Real, EMAX, PERSIST>()), (min_waves<DE
     int64_t t = tile_of<PERSIST>(a, 0);
     if (t < 0) return; // workgroup-uniform
     if constexpr (!PERSIST) {
-        w.run_one(t);
+        // 32 values per thread and the 64-VGPR cap leave no registers to stage tables in
+        w.template run_one<sizeof(Real) == 4 && EMAX == 16 && !DENSE>(t);
     } else {
         const int log2T = w.log2T, T = w.T, tid = w.tid, nthr = w.nthr;
         C v[E];
@@ -563,7 +629,7 @@ __device__ __forceinline__ void ragged_tile(const PassArgs &a, int64_t t, unsign
     constexpr int LMIN = KIND == K_PASS1 ? RAGGED_P1_MIN : RAGGED_P2_MIN;
     if constexpr (L >= LMIN && L <= RAGGED_LMAX) {
         const Tile<Real, (1 << L), 16, KIND, 16, true> w(a, smem);
-        w.run_one(t);
+        w.template run_one<false>(t);
     }
 }
 
@@ -720,6 +786,9 @@ KernelFn pick(int log2N) {
 // pass has at least two stages, so its weight table is published by a stage
 // barrier).
 constexpr int AXIS_LMIN = 5, AXIS_LMAX = 11;
+// Wide axis passes: transforms of 2^31 bytes or more (2^29 complex64 and
+// 2^28 complex128 elements on), whose three factors are at least 2^9.
+constexpr int AXIS_WIDE_LMIN = 9;
 
 template <typename Real> KernelFn pick_default(int kind, int log2N, int rmax) {
     switch (kind * 100 + rmax) {
@@ -730,6 +799,7 @@ template <typename Real> KernelFn pick_default(int kind, int log2N, int rmax) {
     case K_PASS2 * 100 + 16: return pick<Real, K_PASS2, 16>(log2N);
     case K_PASS2 * 100 + 2: return pick<Real, K_PASS2, 2>(log2N);
     case K_AXIS * 100 + 16: return pick<Real, K_AXIS, 16, 0, AXIS_LMIN, AXIS_LMAX>(log2N);
+    case K_AXIS_WIDE * 100 + 16: return pick<Real, K_AXIS_WIDE, 16, 0, AXIS_WIDE_LMIN, AXIS_LMAX>(log2N);
     default: return nullptr;
     }
 }
@@ -771,6 +841,7 @@ template <int PREC> KernelFn pick_mfma_kind(int kind, int log2N) {
 }
 
 KernelFn pick_kernel(int dtype, int kind, int log2N, int rmax, const Variant &v) {
+    if (kind == K_AXIS_WIDE && !v.is_default()) return nullptr;
     if (kind == K_AXIS && !v.is_default()) { // the split exchange (complex64) only
         if (dtype != FFT_C64 || rmax != 16 || v.code() != 2) return nullptr;
         return pick<float, K_AXIS, 16, 2, AXIS_LMIN, AXIS_LMAX>(log2N);
@@ -881,7 +952,7 @@ TileShape tile_shape(int log2N, int rmax, size_t esize, int log2T, const Variant
     const int lsize = int(v.split ? esize / 2 : esize);
     TileShape ts;
     ts.pitch = exchange_pitch(N, T, N / E, lsize, kind != K_SINGLE);
-    ts.lds = lds_bytes(N, rmax, T, E, ts.pitch, lsize, int(esize), kind == K_PASS1 || kind == K_AXIS, v.prec != 0);
+    ts.lds = lds_bytes(N, rmax, T, E, ts.pitch, lsize, int(esize), kind == K_PASS1 || kind >= K_AXIS, v.prec != 0);
     return ts;
 }
 
@@ -968,7 +1039,7 @@ bool plan_pass(Launch &L, int dtype, int kind, int log2N, int rmax, int64_t line
     if (want_T) {
         l2T = ilog2_exact(want_T);
         if (want_T > lines_per_transform || (cap1 && want_T > cap1)) return false;
-    } else if (kind == K_AXIS) { // rows of at least 128 contiguous bytes, 256 threads
+    } else if (kind >= K_AXIS) { // rows of at least 128 contiguous bytes, 256 threads
         l2T = choose_log2T(log2N, rmax, esize, lines_per_transform, 256, int(128 / esize), 0, kind, v);
         if ((int64_t(1) << l2T) * int64_t(esize) < 128) return false;
     } else {
@@ -1240,11 +1311,12 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
             return FFT_E_UNSUPPORTED;
         }
         const int want = o.lines_per_block;
-        if (!plan_pass(p->k1, dtype, K_AXIS, l3, radix, int64_t(1) << l1, batch << (l1 + l2), want, 0, var,
+        const int kind = n * int64_t(esize) > (int64_t(1) << 31) ? K_AXIS_WIDE : K_AXIS;
+        if (!plan_pass(p->k1, dtype, kind, l3, radix, int64_t(1) << l1, batch << (l1 + l2), want, 0, var,
                        p->device) ||
-            !plan_pass(p->k2, dtype, K_AXIS, l2, radix, int64_t(1) << l1, batch << (l1 + l3), want, 0, var,
+            !plan_pass(p->k2, dtype, kind, l2, radix, int64_t(1) << l1, batch << (l1 + l3), want, 0, var,
                        p->device) ||
-            !plan_pass(p->k3, dtype, K_AXIS, l1, radix, int64_t(1) << l3, batch << (l2 + l3), want, 0, var,
+            !plan_pass(p->k3, dtype, kind, l1, radix, int64_t(1) << l3, batch << (l2 + l3), want, 0, var,
                        p->device)) {
             free_plan(p);
             return FFT_E_UNSUPPORTED;

@@ -60,7 +60,7 @@ def test_strerror_covers_codes():
 @pytest.mark.parametrize("n,batch,dtype,want", [
     (0, 1, 0, -1), (1, 1, 0, -1), (3, 1, 0, -1), (1000, 1, 0, -1), (-8, 1, 0, -1),
     (1024, 0, 0, -1), (1024, -5, 1, -1), (1024, 1, 2, -2), (1024, 1, -1, -2),
-    (1 << 29, 1, 0, -8), (1 << 27, 1, 1, -8), (1 << 30, 1, 1, -8), (1 << 20, 1 << 60, 0, -1),
+    (1 << 31, 1, 0, -8), (1 << 30, 1, 1, -8), (1 << 32, 1, 1, -8), (1 << 20, 1 << 60, 0, -1),
 ])
 def test_create_validation(n, batch, dtype, want):
     L = _lib()

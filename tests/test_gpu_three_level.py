@@ -158,43 +158,64 @@ def test_full_oracle_beyond_2p24(lf, torch, t):
     assert err <= 1e-6, err
 
 
-@pytest.mark.parametrize("t", [27, 28])
-def test_properties_at_limit(lf, torch, t):
-    """2^27, 2^28 complex64: a pure tone lands in its bin, the round trip
-    returns n x, and three sampled outputs match the FP64 sum."""
+@pytest.mark.parametrize("t,dtype", [(27, np.complex64), (28, np.complex64), (29, np.complex64),
+                                     (30, np.complex64), (28, np.complex128), (29, np.complex128)],
+                         ids=["c64-27", "c64-28", "c64-29", "c64-30", "c128-28", "c128-29"])
+def test_properties_at_limit(lf, torch, t, dtype):
+    """Up to the largest lengths (2^30 complex64, 2^29 complex128: 8 GiB per
+    buffer; from 2^29 / 2^28 on the passes address the transform in 64
+    bits): a pure tone lands in its bin, the round trip returns n x, and
+    sampled outputs match the FP64 sum."""
     n = 1 << t
-    plan = lf.Plan(n, 1, torch.complex64, flags=THREE)
+    tdt = torch.complex64 if dtype == np.complex64 else torch.complex128
+    tol = 1e-6 if dtype == np.complex64 else 1e-12
+    plan = lf.Plan(n, 1, tdt, flags=THREE)
+    assert plan.info()["levels"] == 3
     a = 98765 % n
     j = torch.arange(n, device="cuda", dtype=torch.int64)
     ang = (j * a % n).to(torch.float64) * (2 * np.pi / n)
-    x = torch.complex(torch.cos(ang), torch.sin(ang)).to(torch.complex64)
-    del ang, j
+    del j
+    x = torch.complex(torch.cos(ang), torch.sin(ang)).to(tdt)
+    del ang
     y = torch.empty_like(x)
-    announce("three-level limit n=2^%d tone" % t)
+    announce("three-level limit n=2^%d %s tone" % (t, np.dtype(dtype).name))
     plan.execute(x, y, -1)
     torch.cuda.synchronize()
-    expect = torch.zeros_like(y)
-    expect[a] = n
-    err = float(torch.linalg.vector_norm((y - expect).to(torch.complex128)) / n)
-    assert err <= 1e-6, err
-    del expect
-    x_np = datagen.signals(n, 1, np.complex64, "normal", 990 + t)[0]
+    y[a] -= n
+    err = float(torch.linalg.vector_norm(y.to(torch.complex128)) / n)
+    assert err <= tol, err
+    del x
+    torch.cuda.empty_cache()
+    x_np = datagen.signals(n, 1, dtype, "normal", 990 + t)[0]
     x = to_dev(x_np)
-    announce("three-level limit n=2^%d round trip" % t)
+    announce("three-level limit n=2^%d %s round trip" % (t, np.dtype(dtype).name))
     plan.execute(x, y, -1)
     z = torch.empty_like(y)
     plan.execute(y, z, 1)
     torch.cuda.synchronize()
     rt = float(torch.linalg.vector_norm((z / n - x).to(torch.complex128)) /
                torch.linalg.vector_norm(x.to(torch.complex128)))
-    assert rt <= 2e-6, rt
+    assert rt <= 2 * tol, rt
+    del z
     y_np = to_np(y)
+    plan.destroy()
     rms = np.sqrt(np.mean(np.abs(y_np.astype(np.complex128)) ** 2))
-    for k in datagen.sample_indices(n, 3, seed=t):
+    for k in datagen.sample_indices(n, 3 if t <= 28 else 2, seed=t):
         announce("three-level limit n=2^%d sample k=%d" % (t, k))
         ref = dft_at(x_np, int(k), -1)
-        assert abs(y_np[k] - ref) <= 1e-5 * rms, (k, y_np[k], ref)
-    plan.destroy()
+        assert abs(y_np[k] - ref) <= 10 * tol * rms, (k, y_np[k], ref)
+
+
+def test_full_oracle_c128_2p27(lf, torch):
+    """The largest complex128 length still addressed with buffer descriptors,
+    against the full oracle."""
+    t = 27
+    x_np = datagen.signals(1 << t, 1, np.complex128, "normal", 1027)
+    announce("three-level n=2^27 c128 forward")
+    got, info = run3(lf, x_np, -1)
+    assert info["levels"] == 3
+    err = oracle.rel_l2(got[0], oracle.fft(x_np[0], -1))
+    assert err <= 1e-12, err
 
 
 def test_timing_precision_and_errors(lf, torch):
