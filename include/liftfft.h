@@ -271,10 +271,11 @@ int fft_plan_get_info(const fft_plan *plan, fft_plan_info *info);
  * a power of two.  This is a different arithmetic from the paper's radix-2
  * butterflies (same transform, larger rounding error: about 1e-6 relative
  * L2 for FP16 pairs, 1e-5 for BF16 pairs); tests state the measured error.
- * Available for complex64 single-pass and two-level plans (not three-level
- * ones: create those with FFT_OPT_TWO_LEVEL from 2^24 on) whose pass lines are 16, 256 or 4096 points
- * (every stage radix 16) with radix 16, 16 values per thread and one tile
- * per workgroup; otherwise FFT_E_UNSUPPORTED and the plan is unchanged.
+ * Available for complex64 single-pass and two-level plans whose pass lines
+ * are 16, 256 or 4096 points, and three-level plans whose lines are all 256
+ * points (n = 2^24), each stage radix 16, with radix 16, 16 values per
+ * thread and one tile per workgroup; otherwise FFT_E_UNSUPPORTED and the
+ * plan is unchanged.
  * FFT_E_ARG for an unknown mode.  Takes effect for later executes.
  */
 enum { FFT_PREC_FP32 = 0, FFT_PREC_F16X2 = 1, FFT_PREC_BF16X2 = 2 };

@@ -835,21 +835,24 @@ template <int KIND, int PREC> KernelFn pick_mfma(int log2N) {
     }
 }
 template <int PREC> KernelFn pick_mfma_kind(int kind, int log2N) {
+    if (kind == K_AXIS) // three-level passes over 256-point lines (n = 2^24 = 256^3)
+        return log2N == 8 ? &pass_kernel<float, 256, 16, K_AXIS, 16, false, false, false, PREC> : nullptr;
+    if (kind == K_AXIS_WIDE) return nullptr;
     return kind == K_SINGLE ? pick_mfma<K_SINGLE, PREC>(log2N)
            : kind == K_PASS1 ? pick_mfma<K_PASS1, PREC>(log2N)
                              : pick_mfma<K_PASS2, PREC>(log2N);
 }
 
 KernelFn pick_kernel(int dtype, int kind, int log2N, int rmax, const Variant &v) {
-    if (kind == K_AXIS_WIDE && !v.is_default()) return nullptr;
-    if (kind == K_AXIS && !v.is_default()) { // the split exchange (complex64) only
-        if (dtype != FFT_C64 || rmax != 16 || v.code() != 2) return nullptr;
-        return pick<float, K_AXIS, 16, 2, AXIS_LMIN, AXIS_LMAX>(log2N);
-    }
     if (v.prec) {
         if (dtype != FFT_C64 || rmax != 16 || v.emax != 16 || v.split || v.persist || v.dense) return nullptr;
         return v.prec == PREC_F16X2 ? pick_mfma_kind<PREC_F16X2>(kind, log2N)
                                     : pick_mfma_kind<PREC_BF16X2>(kind, log2N);
+    }
+    if (kind == K_AXIS_WIDE && !v.is_default()) return nullptr;
+    if (kind == K_AXIS && !v.is_default()) { // the split exchange (complex64) only
+        if (dtype != FFT_C64 || rmax != 16 || v.code() != 2) return nullptr;
+        return pick<float, K_AXIS, 16, 2, AXIS_LMIN, AXIS_LMAX>(log2N);
     }
     if (v.is_default())
         return dtype == FFT_C64 ? pick_default<float>(kind, log2N, rmax)
@@ -898,7 +901,7 @@ struct fft_plan {
     Launch k1, k2, k3; // k3: third pass of a three-level lift
     int log2n1 = 0, log2n2 = 0, log2n3 = 0; // three-level lift n = n1 n2 n3 (n1 contiguous)
     const void *tw3 = nullptr;
-    Variant base1, base2; // the variants chosen at creation (precision FP32)
+    Variant base1, base2, base3; // the variants chosen at creation (precision FP32)
     int log2W = 0;        // scratch slab width (two-pass plans)
     bool no_remap = false;
     int precision = 0;
@@ -1376,6 +1379,7 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
     p->no_remap = (o.flags & FFT_OPT_NO_XCD_REMAP) != 0;
     p->base1 = p->k1.var;
     p->base2 = p->k2.var;
+    p->base3 = p->k3.var;
     if (!p->k1.fn || (p->passes >= 2 && !p->k2.fn) || (p->passes == 3 && !p->k3.fn)) {
         free_plan(p);
         return FFT_E_UNSUPPORTED;
@@ -1879,8 +1883,8 @@ int fft_plan_get_info(const fft_plan *p, fft_plan_info *info) {
 int fft_plan_set_precision(fft_plan *p, int mode) {
     if (!p) return FFT_E_NULL;
     if (mode != FFT_PREC_FP32 && mode != FFT_PREC_F16X2 && mode != FFT_PREC_BF16X2) return FFT_E_ARG;
-    if (p->ragged || p->passes == 3) return mode == FFT_PREC_FP32 ? FFT_OK : FFT_E_UNSUPPORTED;
-    Launch n1 = p->k1, n2 = p->k2;
+    if (p->ragged) return mode == FFT_PREC_FP32 ? FFT_OK : FFT_E_UNSUPPORTED;
+    Launch n1 = p->k1, n2 = p->k2, n3 = p->k3;
     auto redo = [&](Launch &L, const Variant &base) {
         Variant v = base;
         if (mode != FFT_PREC_FP32) {
@@ -1891,9 +1895,11 @@ int fft_plan_set_precision(fft_plan *p, int mode) {
         if (p->no_remap) L.remap = false;
         return true;
     };
-    if (!redo(n1, p->base1) || (p->passes == 2 && !redo(n2, p->base2))) return FFT_E_UNSUPPORTED;
+    if (!redo(n1, p->base1) || (p->passes >= 2 && !redo(n2, p->base2)) || (p->passes == 3 && !redo(n3, p->base3)))
+        return FFT_E_UNSUPPORTED;
     p->k1 = n1;
     p->k2 = n2;
+    p->k3 = n3;
     p->precision = mode;
     return FFT_OK;
 }

@@ -82,6 +82,29 @@ def test_transform_error(lf, mode, t, batch, log2_p):
         assert max(errs) <= BOUND[mode], (mode, t, sign, errs)
 
 
+@pytest.mark.parametrize("mode", ["f16x2", "bf16x2"])
+def test_three_level_2p24(lf, torch, mode):
+    """The default plan at n = 2^24 (three levels, 256 x 256 x 256, every
+    stage radix 16) with its three axis passes on the matrix cores, both
+    signs, against the oracle."""
+    n = 1 << 24
+    x_np = datagen.signals(n, 1, np.complex64, "normal", 64)
+    plan = lf.Plan(n, 1, torch.complex64)
+    assert plan.info()["levels"] == 3
+    plan.set_precision(mode)
+    assert plan.info()["precision"] == {"f16x2": 1, "bf16x2": 2}[mode]
+    x = to_dev(x_np)
+    y = torch.full_like(x, float("nan"))
+    for sign in (-1, 1):
+        announce("precision three-level n=2^24 %s sign=%d" % (mode, sign))
+        plan.execute(x, y, sign)
+        torch.cuda.synchronize()
+        err = oracle.rel_l2(to_np(y)[0], oracle.fft(x_np[0].astype(np.complex128), sign))
+        print("three-level 2^24 %s sign %d: rel L2 %.3e" % (mode, sign, err))
+        assert err <= BOUND[mode], (mode, sign, err)
+    plan.destroy()
+
+
 def test_config4_sampled(lf, torch):
     """Config 4: 256 transforms of 2^20, N(0,1) (seed 4), lifted 4096 x 256,
     with FP16 and BF16 pairs: eight sampled transforms against the oracle, and
@@ -126,6 +149,7 @@ def test_precision_switching_and_errors(lf, torch):
     assert e.value.code == -9
     plan.destroy()
     for make in (lambda: lf.Plan(1 << 22, 1, torch.complex64),            # 2048-point lines
+                 lambda: lf.Plan(1 << 25, 1, torch.complex64),            # three levels, 512-point lines
                  lambda: lf.Plan(1 << 12, 1, torch.complex128),           # complex128
                  lambda: lf.Plan(1 << 12, 1, torch.complex64, radix=2),   # radix-2 stages
                  lambda: lf.Plan.uneven([256, 4096], torch.complex64)):   # uneven batch

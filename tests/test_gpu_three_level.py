@@ -231,7 +231,7 @@ def test_timing_precision_and_errors(lf, torch):
     assert cnt == [3, 3, 3] and min(ms) > 0
     plan.set_precision("fp32")
     with pytest.raises(lf.FFTError) as e:
-        plan.set_precision("f16x2")
+        plan.set_precision("f16x2")  # 2^20 = 128 x 64 x 128: lines not all radix 16
     assert e.value.code == -8
     plan.destroy()
     for t, opts, code in ((14, {}, -8), (20, dict(radix=2), -8), (20, dict(lines_per_block=3), -9),
