@@ -6,7 +6,9 @@ Same tolerances as the two-level path: relative L2 per transform <= 1e-6
 the GPU received.  Sizes span every factorisation the plan makes from
 2^15 = 32^3 up to 2^24 = 256^3 (full oracle), batches with more than one
 transform, both signs, in-place execution, and 2^25..2^28 complex64 (full
-oracle at 2^25/2^26; tone, round trip and sampled frequencies above).
+oracle at 2^25/2^26 and complex128 2^27; tone, round trip and sampled
+frequencies at 2^28 and at the largest lengths, 2^30 complex64 and 2^29
+complex128).
 """
 import numpy as np
 import pytest
@@ -158,14 +160,13 @@ def test_full_oracle_beyond_2p24(lf, torch, t):
     assert err <= 1e-6, err
 
 
-@pytest.mark.parametrize("t,dtype", [(27, np.complex64), (28, np.complex64), (29, np.complex64),
-                                     (30, np.complex64), (28, np.complex128), (29, np.complex128)],
-                         ids=["c64-27", "c64-28", "c64-29", "c64-30", "c128-28", "c128-29"])
+@pytest.mark.parametrize("t,dtype", [(28, np.complex64), (30, np.complex64), (29, np.complex128)],
+                         ids=["c64-28", "c64-30", "c128-29"])
 def test_properties_at_limit(lf, torch, t, dtype):
-    """Up to the largest lengths (2^30 complex64, 2^29 complex128: 8 GiB per
-    buffer; from 2^29 / 2^28 on the passes address the transform in 64
-    bits): a pure tone lands in its bin, the round trip returns n x, and
-    sampled outputs match the FP64 sum."""
+    """The largest lengths: 2^28 complex64 (the last addressed with 32-bit
+    buffer offsets) and 2^30 complex64 / 2^29 complex128 (8 GiB per buffer,
+    addressed in 64 bits): a pure tone lands in its bin, the round trip
+    returns n x, and sampled outputs match the FP64 sum."""
     n = 1 << t
     tdt = torch.complex64 if dtype == np.complex64 else torch.complex128
     tol = 1e-6 if dtype == np.complex64 else 1e-12
@@ -200,7 +201,7 @@ def test_properties_at_limit(lf, torch, t, dtype):
     y_np = to_np(y)
     plan.destroy()
     rms = np.sqrt(np.mean(np.abs(y_np.astype(np.complex128)) ** 2))
-    for k in datagen.sample_indices(n, 3 if t <= 28 else 2, seed=t):
+    for k in datagen.sample_indices(n, 3 if t <= 28 else 1, seed=t):
         announce("three-level limit n=2^%d sample k=%d" % (t, k))
         ref = dft_at(x_np, int(k), -1)
         assert abs(y_np[k] - ref) <= 10 * tol * rms, (k, y_np[k], ref)
