@@ -417,7 +417,7 @@ def main() -> int:
         return 0
 
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; --gpus %d is not supported "
+        print("bench.py: measures one GPU only; --gpus %d is not supported "
               "(transforms shard across GPUs without exchange for batches, and with one "
               "all-to-all for a single large transform; neither is built here)" % args.gpus,
               file=sys.stderr)

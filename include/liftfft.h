@@ -58,7 +58,7 @@ enum {
     FFT_E_ALIGN = -5,       /* buffer not aligned to its element size */
     FFT_E_OOM = -6,         /* device allocation failed (nothing leaked) */
     FFT_E_HIP = -7,         /* a HIP runtime call or kernel launch failed */
-    FFT_E_UNSUPPORTED = -8, /* valid request outside what this build supports */
+    FFT_E_UNSUPPORTED = -8, /* valid request outside what the library supports */
     FFT_E_ARG = -9          /* other invalid argument (options, precision mode) */
 };
 

@@ -1228,7 +1228,7 @@ const char *fft_strerror(int code) {
     case FFT_E_ALIGN: return "buffer not aligned to its element size";
     case FFT_E_OOM: return "device allocation failed";
     case FFT_E_HIP: return "HIP runtime call or kernel launch failed";
-    case FFT_E_UNSUPPORTED: return "valid request outside what this build supports";
+    case FFT_E_UNSUPPORTED: return "valid request outside what the library supports";
     case FFT_E_ARG: return "invalid option";
     default: return "unknown status code";
     }
