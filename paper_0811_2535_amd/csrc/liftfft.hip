@@ -20,6 +20,14 @@
 //                          Variants of the pass kernels: values per thread,
 //                          split exchange, persistent prefetch, register cap,
 //                          and radix-16 stages on the matrix cores.
+//   pass_kernel<K_AXIS>    one pass of the three-level lift n = n1*n2*n3
+//                          (dimension lifting taken one level further,
+//                          Section 1): transforms along one axis of x viewed
+//                          as n3 x n2 x n1, each tile T adjacent lines of the
+//                          contiguous axis, passes A and B with their
+//                          inter-pass weights fused into the store;
+//                          K_AXIS_WIDE is the same for transforms of 2^31
+//                          bytes or more, addressed in 64 bits.
 //   ragged_kernel          persistent pass 1 / pass 2 over the lifted length
 //                          classes of a packed batch of uneven lengths.
 //   twiddle_table_kernel   FP64 generation of the weight tables.
@@ -60,8 +68,8 @@ struct PassArgs {
     const void *in;
     void *out;
     const void *tw;    // w_N^e, e < N (+1 root), N = this pass's line length
-    const void *tw_hi; // pass 1: w_n^(a * 2^log2h), a < n / 2^log2h
-    const void *tw_lo; // pass 1: w_n^b, b < 2^log2h
+    const void *tw_hi; // weighted passes: w_n^(a * 2^log2h), a < n / 2^log2h
+    const void *tw_lo; // weighted passes: w_n^b, b < 2^log2h
     int64_t lines;     // batch * lines per transform
     int64_t n;         // transform length
     int64_t ntiles;    // tiles of T lines
