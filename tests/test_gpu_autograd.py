@@ -49,9 +49,11 @@ def test_gradcheck_c128(torch):
 
 
 @pytest.mark.parametrize("t,batch,dt,tol", [(12, 2, np.complex128, 1e-12),
-                                            (22, 8, np.complex64, 1e-6)])
+                                            (22, 8, np.complex64, 1e-6),
+                                            (24, 1, np.complex64, 1e-6)])
 def test_weighted_power_loss_gradient(torch, t, batch, dt, tol):
-    """Config 5 at n = 2^22, batch 8 (and a small c128 case)."""
+    """Config 5 at n = 2^22, batch 8 (and a small c128 case); at 2^24 the
+    transform and its adjoint run through the three-level lift."""
     import paper_0811_2535_amd as lf
     n = 1 << t
     x_np = datagen.signals(n, batch, dt, "normal", 5)
@@ -64,6 +66,8 @@ def test_weighted_power_loss_gradient(torch, t, batch, dt, tol):
     loss = (w * (y.real ** 2 + y.imag ** 2)).sum()
     loss.backward()
     torch.cuda.synchronize()
+    if t >= 24:
+        assert lf.cached_plan(n, batch, x.dtype, x.device).info()["levels"] == 3
     g = to_np(x.grad)
     xr = x_np.astype(np.complex128)
     Fx = oracle.fft_batch(xr, -1)
@@ -78,7 +82,7 @@ def test_weighted_power_loss_gradient(torch, t, batch, dt, tol):
     # cancel, and it is exact for this quadratic loss up to rounding.
     h = 1e-3
     k = np.arange(n)
-    idx = datagen.sample_indices(batch * n, 64, seed=55)
+    idx = datagen.sample_indices(batch * n, 64 if t < 24 else 16, seed=55)
     for flat in idx:
         b, j = divmod(int(flat), n)
         c = np.exp(-2j * np.pi * ((j * k) % n) / n)
