@@ -288,20 +288,22 @@ def measure_ragged(torch, lf, datagen, reps: int = 10) -> dict:
             "grid": [info["grid_pass1"], info["grid_pass2"]]}
 
 
-def measure_precision(torch, lf, datagen, reps: int = 5) -> dict:
+def measure_precision(torch, lf, datagen, reps: int = 5):
     """Precision forms on 256 transforms of 2^20 complex64 (N(0,1), seed 4),
     lifted 4096 x 256 so every stage is radix 16: FP32 stages on the vector
     units against radix-16 stages on the matrix cores with FP16 / BF16 pairs.
-    Error: relative L2 of transform 0 against the FP64 oracle."""
+    Reports each form's relative L2 difference from the FP32 path on all
+    transforms; returns also transform 0's input and outputs, whose error
+    against the FP64 oracle the CPU-baseline leg adds."""
     import numpy as np
 
-    import oracle
     n, batch = 1 << 20, 256
     dev = torch.device("cuda:0")
     x_np = datagen.signals(n, batch, np.complex64, "normal", 4)
     x = torch.from_numpy(x_np).to(dev)
     y = torch.empty_like(x)
-    ref0 = oracle.fft(x_np[0].astype(np.complex128), -1)
+    y32 = None
+    firsts = {}
     plan = lf.Plan(n, batch, torch.complex64, log2_p=8)
     out = {"workload": "256 x 2^20 c64 forward, lift 4096 x 256 (all stages radix 16)"}
     flops = 5.0 * n * math.log2(n) * batch
@@ -316,12 +318,27 @@ def measure_precision(torch, lf, datagen, reps: int = 5) -> dict:
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        err = oracle.rel_l2(y[0].cpu().numpy(), ref0)
+        if y32 is None:
+            y32 = y.clone()
+        diff = float(torch.linalg.vector_norm((y - y32).to(torch.complex128)) /
+                     torch.linalg.vector_norm(y32.to(torch.complex128)))
+        firsts[mode] = y[0].cpu().numpy()
         out[mode] = {"ms": round(ms, 4), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
                      "hbm_gbps_algorithmic": round(32 * n * batch / (ms * 1e-3) / 1e9, 1),
-                     "rel_l2_transform0": float("%.3g" % err)}
+                     "rel_l2_vs_fp32_path": float("%.3g" % diff)}
     plan.destroy()
-    return out
+    del y32
+    return out, (x_np[0], firsts)
+
+
+def precision_oracle_errors(x0, firsts):
+    """CPU-baseline leg: relative L2 of each precision form's transform 0
+    against the FP64 oracle."""
+    import numpy as np
+
+    import oracle
+    ref = oracle.fft(x0.astype(np.complex128), -1)
+    return {mode: float("%.3g" % oracle.rel_l2(y, ref)) for mode, y in firsts.items()}
 
 
 def measure_three_level(torch, lf, xs, S, steps, warmup, stream, n):
@@ -572,6 +589,7 @@ def main() -> int:
         "wall_s": round(wall, 4),
         "three_level": three,
     }
+    precision_firsts = None
     if not args.no_extras:
         print("[bench] forward + adjoint backward, batch 8 x 2^22", file=sys.stderr, flush=True)
         del xs, ys
@@ -580,7 +598,7 @@ def main() -> int:
         print("[bench] batched uneven lengths, 4096 transforms", file=sys.stderr, flush=True)
         result["ragged"] = measure_ragged(torch, lf, datagen)
         print("[bench] precision forms, 256 x 2^20", file=sys.stderr, flush=True)
-        result["precision"] = measure_precision(torch, lf, datagen)
+        result["precision"], precision_firsts = measure_precision(torch, lf, datagen)
         print("[bench] autotuner on the headline shape", file=sys.stderr, flush=True)
         tplan, tres = lf.Plan.tuned(n, 1, torch.complex64, max_candidates=48)
         tplan.destroy()
@@ -593,6 +611,10 @@ def main() -> int:
         base, parity = cpu_baseline(host_inputs[0], host_inputs[1], y0, y1)
         result["cpu_baseline"] = base
         result["parity"] = parity
+        if precision_firsts is not None:
+            errs = precision_oracle_errors(*precision_firsts)
+            for mode, e in errs.items():
+                result["precision"][mode]["rel_l2_transform0_vs_oracle"] = e
     plan.destroy()
     print(json.dumps(result), flush=True)
     return 0
