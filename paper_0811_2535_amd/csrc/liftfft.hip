@@ -1916,8 +1916,10 @@ int fft_plan_set_timing(fft_plan *p, int enable) {
     if (!p) return FFT_E_NULL;
     if (enable && p->ev.empty()) {
         p->ev.assign(size_t(TIMING_RING) * RING_EVENTS, nullptr);
+        // Timing-only events: without the system-scope fence a record does not
+        // write back and invalidate the caches between the passes it brackets.
         for (auto &e : p->ev) {
-            if (hipEventCreate(&e) != hipSuccess) {
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
                 (void)hipGetLastError();
                 e = nullptr;
                 return FFT_E_HIP;
@@ -2105,7 +2107,8 @@ int fft_plan_create_tuned(int64_t n, int64_t batch, int dtype, int32_t max_candi
     b.count = n * batch;
     const size_t bytes = size_t(b.count) * best->esize;
     if (hipStreamCreateWithFlags(&b.st, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreate(&b.e0) != hipSuccess || hipEventCreate(&b.e1) != hipSuccess) {
+        hipEventCreateWithFlags(&b.e0, hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&b.e1, hipEventDisableSystemFence) != hipSuccess) {
         (void)hipGetLastError();
         fft_plan_destroy(best);
         return FFT_E_HIP;
