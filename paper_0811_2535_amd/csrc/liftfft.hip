@@ -251,6 +251,38 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
             for (int s = 0; s < E; ++s) v[s] = src[int64_t(slot_off<N, E, R0>(s)) << a.ax_in[2]];
         } else if constexpr (KIND == K_AXIS) {
             const rsrc_t src = make_rsrc(in + base(line0 >> a.ax_log2L), uint32_t(a.n) * ES);
+            if constexpr (!SPLIT && PREC == PREC_FP32 && TILE) {
+                if (a.ax_in[2] == 0) {
+                    // Pass C's lines are contiguous rows: read them row first
+                    // (a wavefront instruction covers TPL consecutive elements
+                    // of each of 64/TPL lines instead of 64/T elements of each
+                    // of T lines) and hand the values to their line-first
+                    // owners through the LDS tile.  Every thread reaches both
+                    // barriers: axis tiles are whole (T divides the lines).
+                    const int cr = tid / TPL, jr = tid % TPL;
+                    const uint32_t l = uint32_t(line0 & ((int64_t(1) << a.ax_log2L) - 1));
+                    const uint32_t lm = l & ((1u << a.ax_log2U) - 1), ld = l >> a.ax_log2U;
+                    const uint32_t rlane = (((lm + uint32_t(cr)) << a.ax_in[0]) + (ld << a.ax_in[1]) + uint32_t(jr)) * ES;
+                    C t[E];
+#pragma unroll
+                    for (int s = 0; s < E; ++s) t[s] = buf_load(in, src, rlane, uint32_t(slot_off<N, E, R0>(s)) * ES);
+                    C *wl = tile + cr * a.pitch;
+#pragma unroll
+                    for (int s = 0; s < E; ++s) {
+                        const int e = jr + slot_off<N, E, R0>(s);
+                        wl[e + (e >> 4)] = t[s];
+                    }
+                    __syncthreads();
+                    const C *rl = tile + c * a.pitch;
+#pragma unroll
+                    for (int s = 0; s < E; ++s) {
+                        const int e = j + slot_off<N, E, R0>(s);
+                        v[s] = rl[e + (e >> 4)];
+                    }
+                    __syncthreads(); // the stage loop's first exchange writes the tile
+                    return;
+                }
+            }
             const uint32_t lane = axis_lane(line0, a.ax_in);
 #pragma unroll
             for (int s = 0; s < E; ++s)
