@@ -89,8 +89,9 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out);
  *   log2_p        force the lift n = p*q with p = 2^log2_p (1 <= log2_p < t);
  *                 forces the two-pass path even when n fits one workgroup.
  *   radix         largest butterfly radix used inside each pass: 2, 4, 8
- *                 or 16 (default 16).  radix = 2 gives the paper's plain
- *                 radix-2 stage loop within each pass.
+ *                 or 16 (default 16).  radix = 2 runs self-sorting radix-2
+ *                 stages within each pass (the paper's own in-place loop on
+ *                 bit-reversed input is fft_plan_create_paper).
  *   lines_per_block   lines (independent short transforms) per workgroup in
  *                     pass 1, or in the single pass (0 = default; power of two).
  *   lines_per_block2  lines per workgroup in pass 2 (0 = default; power of two).
@@ -169,6 +170,32 @@ typedef struct fft_plan_opts {
     int32_t scratch_width;
 } fft_plan_opts;
 
+/*
+ * The paper's own partitioned plan, on the GPU (Sections 4.2-4.8, Fig. 4.9;
+ * the processors' phases of Sections 4.6-4.7): the transform as the paper
+ * states it, for exploring its breakpoints, not the fast path.  m = 2^log2_m
+ * workgroups play the paper's m processors, each owning psize = n/m elements.
+ * The input is read through the bit-reversal permutation P_n (Fig. 2.1);
+ * processor p runs the radix-2 stages 1 .. breakpoint-1 of the in-place
+ * stage loop on its contiguous block [p*psize, (p+1)*psize) (the block
+ * phase), the data is redistributed so that processor p owns the indices
+ * congruent to p mod m, and stages breakpoint .. t run on that private copy
+ * with the weightcyclic factors w_L^(m*r' + p) (the cyclic phase).  The
+ * output is in natural order and equals fft_execute of any other plan up to
+ * rounding.  Private copies are held in LDS when psize elements fit one
+ * workgroup (160 KB), else in global memory.
+ *   log2_m      0 <= log2_m, psize >= m (2*log2_m <= t), else FFT_E_ARG
+ *   breakpoint  log2_m + 1 <= breakpoint <= log2(psize) + 1 (Section 4.8),
+ *               else FFT_E_ARG
+ * Lengths up to 2^20 (FFT_E_UNSUPPORTED above); the plan owns an n*batch
+ * scratch array (the block phase's output) and the n/2 weights w_n^e,
+ * computed in FP64 from their integer exponents.  Executed with fft_execute
+ * (both signs; sign +1 is the paper's own exponent).  Errors otherwise as
+ * fft_plan_create.
+ */
+int fft_plan_create_paper(int64_t n, int64_t batch, int dtype, int32_t log2_m, int32_t breakpoint,
+                          fft_plan **plan_out);
+
 /* As fft_plan_create with explicit options (opts may be NULL). */
 
 int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts *opts,
@@ -189,14 +216,15 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
  * (in, out, sign) triple (captured on a private stream the first time; up to
  * 16 per plan; then, or when the execute stream is itself being captured,
  * the kernels are launched directly).  Replays measure a few percent slower
- * than direct launches on MI355X, hence the default.  opts may be NULL;
- * only flags = FFT_OPT_GRAPH is accepted, anything else returns FFT_E_ARG.
+ * than direct launches on MI355X, hence the default.  flags is 0 or
+ * FFT_OPT_GRAPH; any other bit returns FFT_E_ARG.
  * Errors: FFT_E_NULL (lengths or plan_out NULL), FFT_E_SIZE (count < 1, a
- * length not a power of two >= 2), FFT_E_UNSUPPORTED (a length above the
- * maximum, or a packed buffer of 2^32 bytes or more).
+ * length not a power of two >= 2), FFT_E_ARG (unknown flags),
+ * FFT_E_UNSUPPORTED (a length above the maximum, or a packed buffer of 2^32
+ * bytes or more).
  */
 enum { FFT_OPT_GRAPH = 64 };
-int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const fft_plan_opts *opts,
+int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, uint32_t flags,
                          fft_plan **plan_out);
 
 /*
@@ -208,6 +236,11 @@ int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const
  *   stream    hipStream_t to launch on (NULL = the null stream).
  * Asynchronous: returns after enqueueing the kernels; no host synchronisation
  * and no allocation.  Returns FFT_E_HIP if a launch fails.
+ * The plan's transform (lift, kernels, tables) is read-only here; the plan
+ * also holds bookkeeping that an execute updates -- the timing event ring
+ * (fft_plan_set_timing) and, for uneven batches with FFT_OPT_GRAPH, the
+ * captured-graph cache -- which is why one plan is for one host thread at a
+ * time.
  */
 int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void *stream);
 
@@ -220,7 +253,9 @@ const char *fft_strerror(int code);
 
 /*
  * Plan description, for tests and benchmarks.
- *   passes      1 or 2
+ *   passes      kernel launches per execute: 1 (single pass), 2 (two-level
+ *               lift, or an uneven batch with lifted lengths) or 3
+ *               (three-level lift)
  *   log2_p      lift: p = 2^log2_p (0 for single-pass plans)
  *   log2_q      lift: q = 2^log2_q (single pass: log2 n)
  *   radix       largest butterfly radix used
@@ -254,9 +289,13 @@ typedef struct fft_plan_info {
     int32_t precision, reserved0;
     /* levels: passes of a single-length plan (1, 2 or 3; 0 for uneven
      * batches).  Three-level plans: log2 of n1, n2, n3 (log2_p = log2_q = 0)
-     * and pass C's launch in the *_pass3 fields (A and B in pass1, pass2). */
+     * and pass C's launch in the *_pass3 fields (A and B in pass1, pass2).
+     * Plans of the paper's partitioned plan (fft_plan_create_paper): log2_p =
+     * log2 m, log2_q = log2 psize, paper_breakpoint = the breakpoint, and the
+     * block / cyclic phase launches in the pass1 / pass2 fields; 0 in
+     * paper_breakpoint otherwise. */
     int32_t levels, log2_n1, log2_n2, log2_n3;
-    int32_t lines_per_block_pass3, grid_pass3, threads_pass3, reserved1;
+    int32_t lines_per_block_pass3, grid_pass3, threads_pass3, paper_breakpoint;
     int64_t lds_bytes_pass3;
 } fft_plan_info;
 
@@ -326,7 +365,7 @@ int fft_plan_create_tuned(int64_t n, int64_t batch, int dtype, int32_t max_candi
                           fft_tune_result *result);
 
 /* ABI version of this header (major*100 + minor). */
-#define LIFTFFT_ABI_VERSION 109
+#define LIFTFFT_ABI_VERSION 200
 int fft_abi_version(void);
 
 #ifdef __cplusplus

@@ -38,8 +38,10 @@
  * tests/test_oracle_pins.py: brute force against oracle_dft for n <= 256,
  * closed forms (delta -> all ones, pure tone -> n*delta, n = 2 and n = 4 by
  * hand), Parseval, linearity, shift theorem, round trip, Hermitian symmetry
- * of real input, a numpy.fft cross-check, and the paper's own loop nests
- * (Fig. 3.9, Fig. 4.9) run literally in Python.
+ * of real input, a numpy.fft cross-check, and an independent numpy
+ * restatement of the paper's staged radix-2 loop and its Section 4
+ * block/cyclic plan (tests/paper_plan.py, written from the prose of
+ * Sections 2-4, not a transcription of the printed loop nests).
  *
  * Build: gcc -O2 -std=c99 -fPIC -shared (no -ffast-math; IEEE round to
  * nearest even).

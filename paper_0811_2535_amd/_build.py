@@ -17,8 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_NAME = "libliftfft.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
-SOURCES = ["liftfft.hip"]
-HEADERS = ["fft_engine.hpp"]
+SOURCES = ["liftfft.hip", "paper_plan.hip"]
+HEADERS = ["fft_engine.hpp", "paper_plan.hpp"]
 ARCH = "gfx950"
 
 
@@ -45,19 +45,39 @@ def compile_flags() -> list[str]:
 
 
 def build(verbose: bool = True, out: str | None = None) -> str:
-    """Compile every source and link the shared library (always rebuilds)."""
+    """Compile every source (in parallel, one object each) and link the shared
+    library (always rebuilds)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     out = out or LIB_PATH
-    tmp = out + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + compile_flags() + ["-shared", "-o", tmp] + \
-        [os.path.join(CSRC, s) for s in SOURCES]
+    tag = ".tmp%d" % os.getpid()
+    objs = [out + "." + os.path.splitext(s)[0] + tag + ".o" for s in SOURCES]
     t0 = time.time()
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building %s" % LIB_NAME)
-    os.replace(tmp, out)
+
+    def run(cmd):
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        return subprocess.run(cmd, capture_output=True, text=True)
+
+    cmds = [[hipcc()] + compile_flags() + ["-c", "-o", o, os.path.join(CSRC, s)]
+            for s, o in zip(SOURCES, objs)]
+    try:
+        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+            results = list(ex.map(run, cmds))
+        for res, src in zip(results, SOURCES):
+            if res.returncode != 0:
+                sys.stderr.write(res.stdout + res.stderr)
+                raise RuntimeError("hipcc failed compiling %s" % src)
+        tmp = out + tag
+        res = run([hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed linking %s" % LIB_NAME)
+        os.replace(tmp, out)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     if verbose:
         print("built %s in %.1fs" % (out, time.time() - t0), flush=True)
     return out

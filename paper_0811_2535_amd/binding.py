@@ -29,6 +29,7 @@ EXPORTED = [
     "fft_plan_create", "fft_plan_create_ex", "fft_execute", "fft_plan_destroy",
     "fft_strerror", "fft_plan_get_info", "fft_plan_set_timing", "fft_plan_read_timing",
     "fft_abi_version", "fft_plan_create_many", "fft_plan_create_tuned", "fft_plan_set_precision",
+    "fft_plan_create_paper",
 ]
 
 
@@ -91,7 +92,7 @@ class PlanInfo(ctypes.Structure):
                 ("levels", ctypes.c_int32), ("log2_n1", ctypes.c_int32),
                 ("log2_n2", ctypes.c_int32), ("log2_n3", ctypes.c_int32),
                 ("lines_per_block_pass3", ctypes.c_int32), ("grid_pass3", ctypes.c_int32),
-                ("threads_pass3", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("threads_pass3", ctypes.c_int32), ("paper_breakpoint", ctypes.c_int32),
                 ("lds_bytes_pass3", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
@@ -118,10 +119,12 @@ def lib():
             L.fft_plan_create.argtypes = [i64, i64, i32, ctypes.POINTER(vp)]
             L.fft_plan_create_ex.argtypes = [i64, i64, i32, ctypes.POINTER(PlanOpts),
                                              ctypes.POINTER(vp)]
-            L.fft_plan_create_many.argtypes = [ctypes.POINTER(i64), i64, i32, ctypes.POINTER(PlanOpts),
+            L.fft_plan_create_many.argtypes = [ctypes.POINTER(i64), i64, i32, ctypes.c_uint32,
                                                ctypes.POINTER(vp)]
             L.fft_plan_create_tuned.argtypes = [i64, i64, i32, ctypes.c_int32, ctypes.POINTER(vp),
                                                 ctypes.POINTER(TuneResult)]
+            L.fft_plan_create_paper.argtypes = [i64, i64, i32, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.POINTER(vp)]
             L.fft_execute.argtypes = [vp, vp, vp, i32, vp]
             L.fft_plan_destroy.argtypes = [vp]
             L.fft_strerror.argtypes = [i32]
@@ -131,7 +134,7 @@ def lib():
             L.fft_plan_set_precision.argtypes = [vp, i32]
             L.fft_plan_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double * 3),
                                                ctypes.POINTER(ctypes.c_int64 * 3), i32]
-            for name in ("fft_plan_create", "fft_plan_create_ex", "fft_plan_create_many",
+            for name in ("fft_plan_create", "fft_plan_create_ex", "fft_plan_create_many", "fft_plan_create_paper",
                          "fft_plan_create_tuned", "fft_plan_set_precision", "fft_execute",
                          "fft_plan_destroy", "fft_plan_get_info", "fft_plan_set_timing",
                          "fft_plan_read_timing", "fft_abi_version"):
@@ -181,6 +184,21 @@ class Plan:
         return self, res.as_dict()
 
     @classmethod
+    def paper(cls, n: int, batch: int = 1, dtype=torch.complex64, log2_m: int = 1,
+              breakpoint: int = 2) -> "Plan":
+        """The paper's partitioned radix-2 plan with m = 2^log2_m processors
+        (workgroups) split at ``breakpoint`` (fft_plan_create_paper)."""
+        self = cls.__new__(cls)
+        self._h = ctypes.c_void_p()
+        self.n, self.batch = int(n), int(batch)
+        self.dtype_code = dtype_code(dtype)
+        self.torch_dtype = torch.complex64 if self.dtype_code == FFT_C64 else torch.complex128
+        rc = lib().fft_plan_create_paper(self.n, self.batch, self.dtype_code, int(log2_m), int(breakpoint),
+                                         ctypes.byref(self._h))
+        _check(rc, "fft_plan_create_paper(n=%d, log2_m=%d, breakpoint=%d)" % (self.n, log2_m, breakpoint))
+        return self
+
+    @classmethod
     def uneven(cls, lengths, dtype=torch.complex64, graph: bool = False) -> "Plan":
         """A plan for transforms of the given power-of-two lengths packed back
         to back in one buffer (fft_plan_create_many); ``self.offsets`` holds
@@ -191,9 +209,8 @@ class Plan:
         arr = (ctypes.c_int64 * max(1, len(lens)))(*lens)
         self.dtype_code = dtype_code(dtype)
         self.torch_dtype = torch.complex64 if self.dtype_code == FFT_C64 else torch.complex128
-        opts = PlanOpts(0, 0, 0, 0, FFT_OPT_GRAPH if graph else 0)
-        rc = lib().fft_plan_create_many(arr, len(lens), self.dtype_code, ctypes.byref(opts),
-                                        ctypes.byref(self._h))
+        flags = FFT_OPT_GRAPH if graph else 0
+        rc = lib().fft_plan_create_many(arr, len(lens), self.dtype_code, flags, ctypes.byref(self._h))
         _check(rc, "fft_plan_create_many(count=%d)" % len(lens))
         self.lengths = lens
         self.offsets = [0] * len(lens)
@@ -281,9 +298,14 @@ class Plan:
 _plans: dict = {}
 
 
-def cached_plan(n: int, batch: int, dtype, device: torch.device) -> Plan:
-    """One plan per (n, batch, dtype, device), created on first use."""
-    key = (int(n), int(batch), dtype, device.index)
+def cached_plan(n: int, batch: int, dtype, device: torch.device, stream=None) -> Plan:
+    """One plan per (n, batch, dtype, device, stream, host thread), created on
+    first use.  A plan's executes share its scratch array, so they must be
+    ordered on one stream; keying the cache on the stream and the calling
+    thread gives work on different streams (or threads) plans of their own."""
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    key = (int(n), int(batch), dtype, device.index, int(stream.cuda_stream), threading.get_ident())
     p = _plans.get(key)
     if p is None:
         with torch.cuda.device(device):
@@ -313,6 +335,7 @@ def fft(x: torch.Tensor, sign: int = -1, out: torch.Tensor | None = None) -> tor
         out = torch.empty_like(x)
     if batch == 0:
         return out
-    plan = cached_plan(n, batch, x.dtype, x.device)
-    plan.execute(x, out, sign)
+    stream = torch.cuda.current_stream(x.device)
+    plan = cached_plan(n, batch, x.dtype, x.device, stream)
+    plan.execute(x, out, sign, stream)
     return out

@@ -49,6 +49,7 @@
 
 #include "fft_engine.hpp"
 #include "liftfft.h"
+#include "paper_plan.hpp"
 
 using namespace liftfft;
 
@@ -956,6 +957,9 @@ struct fft_plan {
     };
     bool ragged = false;
     int length_classes = 0;
+    // The paper's partitioned radix-2 plan (fft_plan_create_paper).
+    bool paper = false;
+    liftfft_paper::PaperPlan pp;
     RaggedLaunch ra, rb;
     struct SingleClass {
         Launch L;
@@ -965,7 +969,10 @@ struct fft_plan {
     void *meta = nullptr; // device: classes and transform offsets
     size_t meta_bytes = 0;
     bool use_graph = false;
-    hipStream_t cap = nullptr; // private stream for graph capture
+    // Execute-time bookkeeping (mutable: fft_execute takes a const plan, whose
+    // transform it only reads): the graph cache of uneven batches and the
+    // timing event ring.
+    mutable hipStream_t cap = nullptr; // private stream for graph capture
     struct GraphEntry {
         const void *in;
         void *out;
@@ -973,14 +980,14 @@ struct fft_plan {
         hipGraph_t graph;
         hipGraphExec_t exec;
     };
-    std::vector<GraphEntry> graphs;
+    mutable std::vector<GraphEntry> graphs;
     // Benchmark timing: a ring of event quadruples (before the first pass,
     // after each pass) recorded on the execute stream; drained on read.
     bool timing = false;
     std::vector<hipEvent_t> ev;
-    int ring_head = 0, ring_count = 0;
-    double ms[3] = {0, 0, 0};
-    int64_t launches[3] = {0, 0, 0};
+    mutable int ring_head = 0, ring_count = 0;
+    mutable double ms[3] = {0, 0, 0};
+    mutable int64_t launches[3] = {0, 0, 0};
 };
 
 namespace {
@@ -1040,6 +1047,9 @@ bool fill_launch(Launch &L, int dtype, int kind, int log2N, int rmax, int log2T,
     if (v.prec && L.threads % 64) return false; // waves own 64 butterflies per stage
     L.kind = kind;
     L.rmax = rmax;
+    // Axis tiles must be whole: pass C's row-first load has two barriers that
+    // every thread of the workgroup reaches, so no tile may be partial.
+    if ((kind == K_AXIS || kind == K_AXIS_WIDE) && (lines & ((int64_t(1) << log2T) - 1))) return false;
     L.ntiles = (lines + (int64_t(1) << log2T) - 1) >> log2T;
     const TileShape ts = tile_shape(log2N, rmax, esize, log2T, v, kind);
     if (ts.lds > LDS_BUDGET) return false;
@@ -1092,15 +1102,15 @@ bool plan_pass(Launch &L, int dtype, int kind, int log2N, int rmax, int64_t line
     return fill_launch(L, dtype, kind, log2N, rmax, l2T, lines, v, device);
 }
 
-int gen_table(int dtype, void *dst, int64_t count, int64_t mult, int log2N) {
+int gen_table(int dtype, void *dst, int64_t count, int64_t mult, int log2N, hipStream_t st = nullptr) {
     const int threads = 256;
     const int64_t blocks = (count + threads - 1) / threads;
     if (dtype == FFT_C64)
-        hipLaunchKernelGGL(twiddle_table_kernel<float>, dim3(unsigned(blocks)), dim3(threads), 0, 0,
+        hipLaunchKernelGGL(twiddle_table_kernel<float>, dim3(unsigned(blocks)), dim3(threads), 0, st,
                            static_cast<float2 *>(dst), count, mult, log2N);
     else
         hipLaunchKernelGGL(twiddle_table_kernel<double>, dim3(unsigned(blocks)), dim3(threads), 0,
-                           0, static_cast<double2 *>(dst), count, mult, log2N);
+                           st, static_cast<double2 *>(dst), count, mult, log2N);
     return hipGetLastError() == hipSuccess ? FFT_OK : FFT_E_HIP;
 }
 
@@ -1114,11 +1124,22 @@ bool default_three_level(int t, int dtype, int radix, const Variant &v) {
     return t >= 24 && radix == 16 && v.is_default();
 }
 
+// Workgroup order of a single-length plan's launches (fill_launch sets the
+// XCD-contiguous remap wherever the grid allows it).  Up to 2^24 passes B and
+// C of the three-level lift run in the hardware workgroup order (measured at
+// 2^24: 160 us against 166 us with every pass remapped; at 2^22 48.1 against
+// 49.0); from 2^26 on remapping every pass is at least as fast.  Applied
+// after plan creation and after every change of the plan's kernels.
+void apply_remap_policy(fft_plan *p) {
+    if (p->passes == 3 && p->log2n <= 24) p->k2.remap = p->k3.remap = false;
+    if (p->no_remap) p->k1.remap = p->k2.remap = p->k3.remap = false;
+}
+
 constexpr int TIMING_RING = 1024, RING_EVENTS = 4;
 
 // Accumulate the durations recorded in ring slot `slot` (waits for them).
-int drain_slot(fft_plan *p, int slot) {
-    hipEvent_t *e = &p->ev[size_t(slot) * RING_EVENTS];
+int drain_slot(const fft_plan *p, int slot) {
+    const hipEvent_t *e = &p->ev[size_t(slot) * RING_EVENTS];
     if (hipEventSynchronize(e[p->passes]) != hipSuccess) return FFT_E_HIP;
     for (int k = 0; k < p->passes; ++k) {
         float t = 0;
@@ -1129,7 +1150,7 @@ int drain_slot(fft_plan *p, int slot) {
     return FFT_OK;
 }
 
-int drain_all(fft_plan *p) {
+int drain_all(const fft_plan *p) {
     int rc = FFT_OK;
     while (p->ring_count > 0) {
         const int slot = (p->ring_head - p->ring_count + TIMING_RING) % TIMING_RING;
@@ -1200,7 +1221,7 @@ constexpr size_t MAX_GRAPHS = 16; // captured graphs kept per plan
 // an (in, out, sign) triple is seen and replayed afterwards.  When the
 // caller's stream is itself being captured, or the cache is full, the
 // kernels are launched directly.  `ev` (optional) brackets the work.
-int execute_ragged(fft_plan *p, const void *in, void *out, int sign, hipStream_t st, hipEvent_t *ev) {
+int execute_ragged(const fft_plan *p, const void *in, void *out, int sign, hipStream_t st, const hipEvent_t *ev) {
     const int inv = sign > 0;
     bool graph = p->use_graph;
     if (graph) {
@@ -1252,32 +1273,56 @@ int execute_ragged(fft_plan *p, const void *in, void *out, int sign, hipStream_t
 }
 
 
-} // namespace
-
-extern "C" {
-
-int fft_abi_version(void) { return LIFTFFT_ABI_VERSION; }
-
-const char *fft_strerror(int code) {
-    switch (code) {
-    case FFT_OK: return "success";
-    case FFT_E_SIZE: return "invalid size: n must be a power of two >= 2, batch >= 1, no overflow";
-    case FFT_E_DTYPE: return "unknown element type";
-    case FFT_E_SIGN: return "sign must be -1 or +1";
-    case FFT_E_NULL: return "required pointer is NULL";
-    case FFT_E_ALIGN: return "buffer not aligned to its element size";
-    case FFT_E_OOM: return "device allocation failed";
-    case FFT_E_HIP: return "HIP runtime call or kernel launch failed";
-    case FFT_E_UNSUPPORTED: return "valid request outside what the library supports";
-    case FFT_E_ARG: return "invalid option";
-    default: return "unknown status code";
-    }
+// Weight-table entries of a single-length plan: one w_N table per pass (N
+// its line length) and, for lifted plans, the two-level w_n table (n/2^h
+// high and 2^h low entries).
+int64_t table_entries(const fft_plan *p) {
+    const bool lifted = p->passes >= 2;
+    const int64_t n1 = int64_t(1) << p->k1.log2N;
+    const int64_t n2 = lifted ? (int64_t(1) << p->k2.log2N) : 0;
+    const int64_t n3 = p->passes == 3 ? (int64_t(1) << p->k3.log2N) : 0;
+    const int64_t nhi = lifted ? (p->n >> p->log2h) : 0;
+    const int64_t nlo = lifted ? (int64_t(1) << p->log2h) : 0;
+    return n1 + n2 + n3 + nhi + nlo;
 }
 
-int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts *opts,
-                       fft_plan **plan_out) {
-    if (!plan_out) return FFT_E_NULL;
-    *plan_out = nullptr;
+// Point the plan's table pointers into p->tables and (if `generate`) fill
+// the tables on stream st (FP64 kernel, each entry from its integer
+// exponent).
+int fill_tables(fft_plan *p, hipStream_t st, bool generate = true) {
+    const bool lifted = p->passes >= 2;
+    const size_t esize = p->esize;
+    const int t = p->log2n;
+    const int64_t n1 = int64_t(1) << p->k1.log2N;
+    const int64_t n2 = lifted ? (int64_t(1) << p->k2.log2N) : 0;
+    const int64_t n3 = p->passes == 3 ? (int64_t(1) << p->k3.log2N) : 0;
+    const int64_t nhi = lifted ? (p->n >> p->log2h) : 0;
+    const int64_t nlo = lifted ? (int64_t(1) << p->log2h) : 0;
+    char *tb = static_cast<char *>(p->tables);
+    p->tw1 = tb;
+    char *t2 = tb + n1 * esize, *t3 = t2 + n2 * esize, *th = t3 + n3 * esize, *tl = th + nhi * esize;
+    if (lifted) {
+        p->tw2 = t2;
+        p->tw3 = t3;
+        p->tw_hi = th;
+        p->tw_lo = tl;
+    }
+    if (!generate) return FFT_OK;
+    int rc = gen_table(p->dtype, tb, n1, 1, p->k1.log2N, st);
+    if (lifted) {
+        if (rc == FFT_OK) rc = gen_table(p->dtype, t2, n2, 1, p->k2.log2N, st);
+        if (rc == FFT_OK && n3) rc = gen_table(p->dtype, t3, n3, 1, p->k3.log2N, st);
+        if (rc == FFT_OK) rc = gen_table(p->dtype, th, nhi, nlo, t, st);
+        if (rc == FFT_OK) rc = gen_table(p->dtype, tl, nlo, 1, t, st);
+    }
+    return rc;
+}
+
+// Validate a single-length request and choose its lift, its launches and
+// the sizes of its device memory (scratch array and weight tables) without
+// touching device memory.  p is a freshly constructed plan; on an error the
+// caller releases it.
+int shape_plan(fft_plan *p, int64_t n, int64_t batch, int dtype, const fft_plan_opts *opts) {
     if (dtype != FFT_C64 && dtype != FFT_C128) return FFT_E_DTYPE;
     const int t = ilog2_exact(n);
     if (t < 1 || batch < 1) return FFT_E_SIZE;
@@ -1321,9 +1366,6 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
     Variant var2 = var;
     if (o.values_per_thread2) var2.emax = o.values_per_thread2;
     const bool forced = !var.is_default() || !var2.is_default();
-
-    fft_plan *p = new (std::nothrow) fft_plan;
-    if (!p) return FFT_E_OOM;
     p->n = n;
     p->batch = batch;
     p->total = n * batch;
@@ -1333,7 +1375,6 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
     p->esize = esize;
     if (hipGetDevice(&p->device) != hipSuccess) {
         (void)hipGetLastError();
-        free_plan(p);
         return FFT_E_HIP;
     }
 
@@ -1350,7 +1391,6 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
         p->log2n2 = t - p->log2n3 - p->log2n1;
         const int l1 = p->log2n1, l2 = p->log2n2, l3 = p->log2n3;
         if (radix != 16 || l2 < AXIS_LMIN || l3 > AXIS_LMAX) {
-            free_plan(p);
             return FFT_E_UNSUPPORTED;
         }
         const int want = o.lines_per_block;
@@ -1361,20 +1401,17 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
                        p->device) ||
             !plan_pass(p->k3, dtype, kind, l1, radix, int64_t(1) << l3, batch << (l2 + l3), want, 0, var,
                        p->device)) {
-            free_plan(p);
             return FFT_E_UNSUPPORTED;
         }
     } else if (o.log2_p == 0 && t <= mline) {
         p->passes = 1;
         p->log2q = t;
         if (forced) { // the other variants are pass kernels only
-            free_plan(p);
             return FFT_E_UNSUPPORTED;
         }
         const int l2T = o.lines_per_block ? ilog2_exact(o.lines_per_block)
                                           : choose_log2T(t, radix, esize, batch, 256, 1, 0, K_SINGLE, var);
         if (!fill_launch(p->k1, dtype, K_SINGLE, t, radix, l2T, batch, var, p->device)) {
-            free_plan(p);
             return FFT_E_UNSUPPORTED;
         }
     } else {
@@ -1382,7 +1419,6 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
         p->log2q = o.log2_p ? t - o.log2_p : (t + 1) / 2;
         p->log2p = t - p->log2q;
         if (p->log2q > mline || p->log2p > mline) {
-            free_plan(p);
             return FFT_E_UNSUPPORTED;
         }
         const int64_t P = int64_t(1) << p->log2p, Q = int64_t(1) << p->log2q;
@@ -1403,32 +1439,22 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
         // Scratch slab width W: pass 1's tile width unless given; pass 2
         // reads W-wide slabs with a separable offset, so W | TPL2.
         if (o.scratch_width > tpl2) {
-            free_plan(p);
             return FFT_E_UNSUPPORTED;
         }
         if (!plan_pass(p->k1, dtype, K_PASS1, p->log2q, radix, P, P * batch, o.lines_per_block,
                        o.scratch_width ? 0 : tpl2, v1, p->device) ||
             !plan_pass(p->k2, dtype, K_PASS2, p->log2p, radix, Q, Q * batch, o.lines_per_block2, 0, v2,
                        p->device)) {
-            free_plan(p);
             return FFT_E_UNSUPPORTED;
         }
         p->log2W = o.scratch_width ? ilog2_exact(o.scratch_width) : p->k1.log2T;
     }
-    if (p->passes == 3 && t <= 24) {
-        // Up to 2^24 passes B and C of the three-level lift run in the
-        // hardware workgroup order (measured at 2^24: 160 us against 166 us
-        // with every pass remapped; at 2^22 48.1 against 49.0); from 2^26 on
-        // remapping every pass is at least as fast.
-        p->k2.remap = p->k3.remap = false;
-    }
-    if (o.flags & FFT_OPT_NO_XCD_REMAP) p->k1.remap = p->k2.remap = p->k3.remap = false;
     p->no_remap = (o.flags & FFT_OPT_NO_XCD_REMAP) != 0;
+    apply_remap_policy(p);
     p->base1 = p->k1.var;
     p->base2 = p->k2.var;
     p->base3 = p->k3.var;
     if (!p->k1.fn || (p->passes >= 2 && !p->k2.fn) || (p->passes == 3 && !p->k3.fn)) {
-        free_plan(p);
         return FFT_E_UNSUPPORTED;
     }
 
@@ -1436,42 +1462,57 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
     // w_N table per pass (N its line length) and the two-level w_n table.
     const bool lifted = p->passes >= 2;
     p->log2h = lifted ? (t + 1) / 2 : 0;
-    const int64_t n1 = int64_t(1) << p->k1.log2N; // first pass's line
-    const int64_t n2 = lifted ? (int64_t(1) << p->k2.log2N) : 0;
-    const int64_t n3 = p->passes == 3 ? (int64_t(1) << p->k3.log2N) : 0;
-    const int64_t nhi = lifted ? (n >> p->log2h) : 0;
-    const int64_t nlo = lifted ? (int64_t(1) << p->log2h) : 0;
-    const int64_t entries = n1 + n2 + n3 + nhi + nlo;
-    p->table_bytes = size_t(entries) * esize;
+    p->table_bytes = size_t(table_entries(p)) * esize;
+    p->scratch_bytes = lifted ? size_t(n) * size_t(batch) * esize : 0;
+    return FFT_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int fft_abi_version(void) { return LIFTFFT_ABI_VERSION; }
+
+const char *fft_strerror(int code) {
+    switch (code) {
+    case FFT_OK: return "success";
+    case FFT_E_SIZE: return "invalid size: n must be a power of two >= 2, batch >= 1, no overflow";
+    case FFT_E_DTYPE: return "unknown element type";
+    case FFT_E_SIGN: return "sign must be -1 or +1";
+    case FFT_E_NULL: return "required pointer is NULL";
+    case FFT_E_ALIGN: return "buffer not aligned to its element size";
+    case FFT_E_OOM: return "device allocation failed";
+    case FFT_E_HIP: return "HIP runtime call or kernel launch failed";
+    case FFT_E_UNSUPPORTED: return "valid request outside what the library supports";
+    case FFT_E_ARG: return "invalid option";
+    default: return "unknown status code";
+    }
+}
+
+int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts *opts,
+                       fft_plan **plan_out) {
+    if (!plan_out) return FFT_E_NULL;
+    *plan_out = nullptr;
+    fft_plan *p = new (std::nothrow) fft_plan;
+    if (!p) return FFT_E_OOM;
+    int rc = shape_plan(p, n, batch, dtype, opts);
+    if (rc != FFT_OK) {
+        free_plan(p);
+        return rc;
+    }
     if (hipMalloc(&p->tables, p->table_bytes) != hipSuccess) {
         (void)hipGetLastError();
         p->tables = nullptr;
         free_plan(p);
         return FFT_E_OOM;
     }
-    if (lifted) {
-        p->scratch_bytes = size_t(n) * size_t(batch) * esize;
-        if (hipMalloc(&p->scratch, p->scratch_bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            p->scratch = nullptr;
-            free_plan(p);
-            return FFT_E_OOM;
-        }
+    if (p->scratch_bytes && hipMalloc(&p->scratch, p->scratch_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p->scratch = nullptr;
+        free_plan(p);
+        return FFT_E_OOM;
     }
-    char *tb = static_cast<char *>(p->tables);
-    p->tw1 = tb;
-    int rc = gen_table(dtype, tb, n1, 1, p->k1.log2N);
-    if (lifted) {
-        char *t2 = tb + n1 * esize, *t3 = t2 + n2 * esize, *th = t3 + n3 * esize, *tl = th + nhi * esize;
-        p->tw2 = t2;
-        p->tw3 = t3;
-        p->tw_hi = th;
-        p->tw_lo = tl;
-        if (rc == FFT_OK) rc = gen_table(dtype, t2, n2, 1, p->k2.log2N);
-        if (rc == FFT_OK && n3) rc = gen_table(dtype, t3, n3, 1, p->k3.log2N);
-        if (rc == FFT_OK) rc = gen_table(dtype, th, nhi, nlo, t);
-        if (rc == FFT_OK) rc = gen_table(dtype, tl, nlo, 1, t);
-    }
+    rc = fill_tables(p, nullptr);
     if (rc == FFT_OK && hipDeviceSynchronize() != hipSuccess) rc = FFT_E_HIP;
     if (rc != FFT_OK) {
         free_plan(p);
@@ -1485,19 +1526,83 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out) {
     return fft_plan_create_ex(n, batch, dtype, nullptr, plan_out);
 }
 
-int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const fft_plan_opts *opts,
+int fft_plan_create_paper(int64_t n, int64_t batch, int dtype, int32_t log2_m, int32_t breakpoint,
+                          fft_plan **plan_out) {
+    if (!plan_out) return FFT_E_NULL;
+    *plan_out = nullptr;
+    if (dtype != FFT_C64 && dtype != FFT_C128) return FFT_E_DTYPE;
+    const int t = ilog2_exact(n);
+    if (t < 1 || batch < 1) return FFT_E_SIZE;
+    const size_t esize = dtype == FFT_C64 ? 8 : 16;
+    if (batch > (INT64_MAX / 4) / n / int64_t(esize)) return FFT_E_SIZE;
+    // m processors with psize = n/m >= m elements each; breakpoints
+    // log2 m + 1 <= bp <= log2 psize + 1 (Section 4.8).
+    if (log2_m < 0 || 2 * log2_m > t) return FFT_E_ARG;
+    if (breakpoint < log2_m + 1 || breakpoint > t - log2_m + 1) return FFT_E_ARG;
+    if (t > liftfft_paper::MAX_LOG2N || (batch << log2_m) > INT32_MAX) return FFT_E_UNSUPPORTED;
+
+    fft_plan *p = new (std::nothrow) fft_plan;
+    if (!p) return FFT_E_OOM;
+    p->n = n;
+    p->batch = batch;
+    p->total = n * batch;
+    p->dtype = dtype;
+    p->log2n = t;
+    p->radix = 2;
+    p->esize = esize;
+    p->passes = 2;
+    p->paper = true;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        (void)hipGetLastError();
+        free_plan(p);
+        return FFT_E_HIP;
+    }
+    p->pp.dtype = dtype;
+    p->pp.log2n = t;
+    p->pp.log2m = log2_m;
+    p->pp.bp = breakpoint;
+    p->pp.batch = batch;
+    if (liftfft_paper::shape(p->pp) != int(hipSuccess)) {
+        (void)hipGetLastError();
+        free_plan(p);
+        return FFT_E_HIP;
+    }
+    // Weights w_n^e, e < n/2, each from its integer exponent in FP64 (the
+    // paper computes every weight directly, Section 3.5).
+    const int64_t half = n / 2;
+    p->table_bytes = size_t(half) * esize;
+    p->scratch_bytes = size_t(n) * size_t(batch) * esize;
+    if (hipMalloc(&p->tables, p->table_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p->tables = nullptr;
+        free_plan(p);
+        return FFT_E_OOM;
+    }
+    if (hipMalloc(&p->scratch, p->scratch_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p->scratch = nullptr;
+        free_plan(p);
+        return FFT_E_OOM;
+    }
+    p->pp.w = p->tables;
+    int rc = gen_table(dtype, p->tables, half, 1, t);
+    if (rc == FFT_OK && hipDeviceSynchronize() != hipSuccess) rc = FFT_E_HIP;
+    if (rc != FFT_OK) {
+        free_plan(p);
+        return rc;
+    }
+    *plan_out = p;
+    return FFT_OK;
+}
+
+int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, uint32_t flags,
                          fft_plan **plan_out) {
     if (!plan_out) return FFT_E_NULL;
     *plan_out = nullptr;
     if (!lengths) return FFT_E_NULL;
     if (dtype != FFT_C64 && dtype != FFT_C128) return FFT_E_DTYPE;
     if (count < 1) return FFT_E_SIZE;
-    fft_plan_opts o;
-    memset(&o, 0, sizeof(o));
-    if (opts) o = *opts;
-    if (o.log2_p || (o.radix && o.radix != 16) || o.lines_per_block || o.lines_per_block2 ||
-        o.values_per_thread || o.values_per_thread2 || o.scratch_width || (o.flags & ~int32_t(FFT_OPT_GRAPH)))
-        return FFT_E_ARG;
+    if (flags & ~uint32_t(FFT_OPT_GRAPH)) return FFT_E_ARG;
     const size_t esize = dtype == FFT_C64 ? 8 : 16;
     const int max_t = RAGGED_MAX_T, mline = max_line(dtype);
     // Lengths, packed offsets and the classes of equal length.
@@ -1529,7 +1634,7 @@ int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const
     p->dtype = dtype;
     p->esize = esize;
     p->radix = 16;
-    p->use_graph = (o.flags & FFT_OPT_GRAPH) != 0;
+    p->use_graph = (flags & FFT_OPT_GRAPH) != 0;
     auto fail = [&](int rc) {
         free_plan(p);
         return rc;
@@ -1745,24 +1850,13 @@ int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, const
     return FFT_OK;
 }
 
-int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void *stream) {
-    if (!plan || !in || !out) return FFT_E_NULL;
-    if (sign != -1 && sign != 1) return FFT_E_SIGN;
-    if ((reinterpret_cast<uintptr_t>(in) % plan->esize) ||
-        (reinterpret_cast<uintptr_t>(out) % plan->esize))
-        return FFT_E_ALIGN;
-    {
-        // Partial overlap of in and out is not allowed (exact aliasing is).
-        const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
-        const uintptr_t bytes = uintptr_t(plan->total) * plan->esize;
-        if (a != b && a < b + bytes && b < a + bytes) return FFT_E_ARG;
-    }
-    fft_plan *p = const_cast<fft_plan *>(plan);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    int cur = -1;
-    if (hipGetDevice(&cur) != hipSuccess) return FFT_E_HIP;
-    if (cur != p->device && hipSetDevice(p->device) != hipSuccess) return FFT_E_HIP;
+} // extern "C"
 
+namespace {
+
+// Enqueue every launch of plan p on stream st (arguments already checked,
+// p's device current).
+int launch_plan(const fft_plan *p, const void *in, void *out, int sign, hipStream_t st) {
     const bool inv = sign > 0;
     PassArgs a;
     memset(&a, 0, sizeof(a));
@@ -1771,7 +1865,7 @@ int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void 
     a.log2q = p->log2q;
     a.log2h = p->log2h;
     int rc = FFT_OK;
-    hipEvent_t *ev = nullptr;
+    const hipEvent_t *ev = nullptr;
     if (p->timing) {
         if (p->ring_count == TIMING_RING) { // oldest slot still pending: drain it first
             const int slot = p->ring_head;
@@ -1783,6 +1877,12 @@ int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void 
     }
     if (p->ragged) {
         if (rc == FFT_OK) rc = execute_ragged(p, in, out, sign, st, ev);
+    } else if (p->paper) {
+        for (int phase = 0; phase < 2 && rc == FFT_OK; ++phase) {
+            rc = liftfft_paper::launch(p->pp, phase, in, out, p->scratch, sign, st) == int(hipSuccess) ? FFT_OK
+                                                                                                      : FFT_E_HIP;
+            if (rc == FFT_OK && ev) rc = hipEventRecord(ev[phase + 1], st) == hipSuccess ? FFT_OK : FFT_E_HIP;
+        }
     } else if (p->passes == 1) {
         a.in = in;
         a.out = out;
@@ -1864,6 +1964,37 @@ int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void 
         p->ring_head = (p->ring_head + 1) % TIMING_RING;
         ++p->ring_count;
     }
+    return rc;
+}
+
+// Checks shared by the execute entry points: pointers, sign, alignment and
+// overlap of the n*batch-element buffers.
+int check_execute(const void *in, void *out, int sign, size_t esize, int64_t total) {
+    if (!in || !out) return FFT_E_NULL;
+    if (sign != -1 && sign != 1) return FFT_E_SIGN;
+    if ((reinterpret_cast<uintptr_t>(in) % esize) || (reinterpret_cast<uintptr_t>(out) % esize))
+        return FFT_E_ALIGN;
+    // Partial overlap of in and out is not allowed (exact aliasing is).
+    const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
+    const uintptr_t bytes = uintptr_t(total) * esize;
+    if (a != b && a < b + bytes && b < a + bytes) return FFT_E_ARG;
+    return FFT_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void *stream) {
+    if (!plan) return FFT_E_NULL;
+    const int chk = check_execute(in, out, sign, plan->esize, plan->total);
+    if (chk != FFT_OK) return chk;
+    const fft_plan *p = plan;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return FFT_E_HIP;
+    if (cur != p->device && hipSetDevice(p->device) != hipSuccess) return FFT_E_HIP;
+    const int rc = launch_plan(p, in, out, sign, st);
     if (cur != p->device) (void)hipSetDevice(cur);
     return rc;
 }
@@ -1897,6 +2028,16 @@ int fft_plan_get_info(const fft_plan *p, fft_plan_info *info) {
     info->variant_pass2 = p->passes == 2 ? p->k2.var.code() : 0;
     info->precision = p->precision;
     info->levels = p->ragged ? 0 : p->passes;
+    if (p->paper) {
+        info->log2_p = p->pp.log2m;
+        info->log2_q = p->log2n - p->pp.log2m;
+        info->paper_breakpoint = p->pp.bp;
+        info->lines_per_block_pass1 = info->lines_per_block_pass2 = 1;
+        info->grid_pass1 = info->grid_pass2 = int32_t(p->batch << p->pp.log2m);
+        info->threads_pass1 = info->threads_pass2 = p->pp.threads;
+        info->lds_bytes_pass1 = info->lds_bytes_pass2 = int64_t(p->pp.lds_bytes);
+        info->variant_pass1 = info->variant_pass2 = 0;
+    }
     if (p->passes == 3 && !p->ragged) {
         info->log2_p = info->log2_q = 0;
         info->log2_n1 = p->log2n1;
@@ -1930,7 +2071,7 @@ int fft_plan_get_info(const fft_plan *p, fft_plan_info *info) {
 int fft_plan_set_precision(fft_plan *p, int mode) {
     if (!p) return FFT_E_NULL;
     if (mode != FFT_PREC_FP32 && mode != FFT_PREC_F16X2 && mode != FFT_PREC_BF16X2) return FFT_E_ARG;
-    if (p->ragged) return mode == FFT_PREC_FP32 ? FFT_OK : FFT_E_UNSUPPORTED;
+    if (p->ragged || p->paper) return mode == FFT_PREC_FP32 ? FFT_OK : FFT_E_UNSUPPORTED;
     Launch n1 = p->k1, n2 = p->k2, n3 = p->k3;
     auto redo = [&](Launch &L, const Variant &base) {
         Variant v = base;
@@ -1938,15 +2079,14 @@ int fft_plan_set_precision(fft_plan *p, int mode) {
             v.split = false; // the matrix-core stages exchange complex elements
             v.prec = mode;
         }
-        if (!fill_launch(L, p->dtype, L.kind, L.log2N, L.rmax, L.log2T, L.lines, v, p->device)) return false;
-        if (p->no_remap) L.remap = false;
-        return true;
+        return fill_launch(L, p->dtype, L.kind, L.log2N, L.rmax, L.log2T, L.lines, v, p->device);
     };
     if (!redo(n1, p->base1) || (p->passes >= 2 && !redo(n2, p->base2)) || (p->passes == 3 && !redo(n3, p->base3)))
         return FFT_E_UNSUPPORTED;
     p->k1 = n1;
     p->k2 = n2;
     p->k3 = n3;
+    apply_remap_policy(p);
     p->precision = mode;
     return FFT_OK;
 }

@@ -110,29 +110,44 @@ def test_null_plan_paths():
 def test_create_many_validation():
     """Argument checks of fft_plan_create_many (all host-side, before any
     device work)."""
-    from paper_0811_2535_amd.binding import PlanOpts
     L = _lib()
 
     def arr(*v):
         return (ctypes.c_int64 * len(v))(*v)
 
     h = ctypes.c_void_p(123)
-    assert L.fft_plan_create_many(None, 1, 0, None, ctypes.byref(h)) == -4
-    assert L.fft_plan_create_many(arr(8), 1, 0, None, None) == -4
-    assert L.fft_plan_create_many(arr(8), 0, 0, None, ctypes.byref(h)) == -1
+    assert L.fft_plan_create_many(None, 1, 0, 0, ctypes.byref(h)) == -4
+    assert L.fft_plan_create_many(arr(8), 1, 0, 0, None) == -4
+    assert L.fft_plan_create_many(arr(8), 0, 0, 0, ctypes.byref(h)) == -1
     assert h.value is None
-    assert L.fft_plan_create_many(arr(8), 1, 7, None, ctypes.byref(h)) == -2
+    assert L.fft_plan_create_many(arr(8), 1, 7, 0, ctypes.byref(h)) == -2
     for bad in ((8, 12), (8, 1), (8, 0), (8, -16)):
-        assert L.fft_plan_create_many(arr(*bad), 2, 0, None, ctypes.byref(h)) == -1, bad
-    assert L.fft_plan_create_many(arr(8, 1 << 25), 2, 0, None, ctypes.byref(h)) == -8
-    assert L.fft_plan_create_many(arr(8, 1 << 25), 2, 1, None, ctypes.byref(h)) == -8
-    assert L.fft_plan_create_many(arr(8, 1 << 29), 2, 0, None, ctypes.byref(h)) == -8
+        assert L.fft_plan_create_many(arr(*bad), 2, 0, 0, ctypes.byref(h)) == -1, bad
+    assert L.fft_plan_create_many(arr(8, 1 << 25), 2, 0, 0, ctypes.byref(h)) == -8
+    assert L.fft_plan_create_many(arr(8, 1 << 25), 2, 1, 0, ctypes.byref(h)) == -8
+    assert L.fft_plan_create_many(arr(8, 1 << 29), 2, 0, 0, ctypes.byref(h)) == -8
     # the packed buffer must stay below 2^32 bytes (32-bit buffer descriptors)
     big = arr(*([1 << 24] * 32))
-    assert L.fft_plan_create_many(big, 32, 0, None, ctypes.byref(h)) == -8
-    for opts in (PlanOpts(0, 2, 0), PlanOpts(3, 0, 0), PlanOpts(0, 0, 4), PlanOpts(0, 0, 0, 2),
-                 PlanOpts(0, 0, 0, 0, 1), PlanOpts(0, 0, 0, 0, 2), PlanOpts(0, 0, 0, 0, 0, 16)):
-        assert L.fft_plan_create_many(arr(8, 16), 2, 0, ctypes.byref(opts), ctypes.byref(h)) == -9
+    assert L.fft_plan_create_many(big, 32, 0, 0, ctypes.byref(h)) == -8
+    # flags: 0 or FFT_OPT_GRAPH; every other bit is refused before any device work
+    for flags in (1, 2, 4, 8, 16, 32, 128, 256, 1 << 31, 0xFFFFFFFF, 64 | 1):
+        assert L.fft_plan_create_many(arr(8, 16), 2, 0, flags, ctypes.byref(h)) == -9, flags
+        assert h.value is None
+
+
+def test_create_many_signature_matches_header():
+    """The header declares fft_plan_create_many with a uint32_t flags word
+    (the boundary's own signature), and the binding passes it as one."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    decl = re.search(r"int\s+fft_plan_create_many\(([^)]*)\)", text).group(1)
+    params = [" ".join(p.split()) for p in decl.split(",")]
+    assert params == ["const int64_t *lengths", "int64_t count", "int dtype", "uint32_t flags",
+                      "fft_plan **plan_out"]
+    execute = re.search(r"int\s+fft_execute\(([^)]*)\)", text).group(1)
+    assert " ".join(execute.split(",")[0].split()) == "const fft_plan *plan"
+    L = _lib()
+    assert L.fft_plan_create_many.argtypes[3] is ctypes.c_uint32
 
 
 def test_create_tuned_validation():
@@ -171,3 +186,20 @@ def test_info_struct_matches_header():
         names += [v.strip() for v in decl.split(",")]
     assert [f for f, _ in PlanInfo._fields_] == names
 
+
+
+def test_create_paper_validation():
+    """fft_plan_create_paper refuses invalid processor counts and breakpoints
+    (Section 4.8: psize >= m, log2 m + 1 <= bp <= log2 psize + 1) before any
+    device work."""
+    L = _lib()
+    h = ctypes.c_void_p(123)
+    t = 12
+    for lm, bp, want in ((-1, 1, -9), (7, 8, -9), (3, 3, -9), (3, 11, -9), (0, 0, -9), (0, 14, -9)):
+        assert L.fft_plan_create_paper(1 << t, 1, 0, lm, bp, ctypes.byref(h)) == want, (lm, bp)
+        assert h.value is None
+    assert L.fft_plan_create_paper(1000, 1, 0, 1, 2, ctypes.byref(h)) == -1
+    assert L.fft_plan_create_paper(1 << 12, 0, 0, 1, 2, ctypes.byref(h)) == -1
+    assert L.fft_plan_create_paper(1 << 12, 1, 5, 1, 2, ctypes.byref(h)) == -2
+    assert L.fft_plan_create_paper(1 << 21, 1, 0, 4, 6, ctypes.byref(h)) == -8
+    assert L.fft_plan_create_paper(1 << 12, 1, 0, 1, 2, None) == -4
