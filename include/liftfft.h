@@ -59,7 +59,8 @@ enum {
     FFT_E_OOM = -6,         /* device allocation failed (nothing leaked) */
     FFT_E_HIP = -7,         /* a HIP runtime call or kernel launch failed */
     FFT_E_UNSUPPORTED = -8, /* valid request outside what the library supports */
-    FFT_E_ARG = -9          /* other invalid argument (options, precision mode) */
+    FFT_E_ARG = -9,         /* other invalid argument (options, precision mode) */
+    FFT_E_CAPACITY = -10    /* beyond the fixed scratch of fft_execute_static */
 };
 
 /* Largest supported log2(n) per element type: one workgroup transforms lines
@@ -243,6 +244,27 @@ int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, uint3
  * time.
  */
 int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void *stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * transform of fft_plan_create(n, batch, dtype) + fft_execute, without a
+ * plan and without any allocation.  The launches, kernels and results are
+ * those of the default plan of the same shape (bit for bit); the inter-pass
+ * scratch array and the weight tables live in one static device array per
+ * GPU (32 MiB + 256 KiB, held by every GPU the library runs on until the
+ * process ends), shared by every call on that GPU.  Capacity: n*batch
+ * elements up to 32 MiB (2^22 complex64, 2^21 complex128); larger requests
+ * return FFT_E_CAPACITY before any device work.
+ *   in, out, sign, stream   as for fft_execute.
+ * The tables are regenerated on `stream` whenever (n, dtype) differs from the
+ * previous call's on that GPU.  Calls that overlap on one GPU (on different
+ * streams, or from different host threads without ordering their streams)
+ * race on the shared array and give wrong results; order them.  Errors as
+ * fft_plan_create and fft_execute, plus FFT_E_CAPACITY.
+ */
+int fft_execute_static(int64_t n, int64_t batch, int dtype, const void *in, void *out, int sign,
+                       void *stream);
 
 /* Release a plan.  NULL-safe.  The caller must have synchronised every stream
  * that used the plan. */

@@ -23,13 +23,13 @@ FFT_OK = 0
 STATUS = {
     0: "FFT_OK", -1: "FFT_E_SIZE", -2: "FFT_E_DTYPE", -3: "FFT_E_SIGN", -4: "FFT_E_NULL",
     -5: "FFT_E_ALIGN", -6: "FFT_E_OOM", -7: "FFT_E_HIP", -8: "FFT_E_UNSUPPORTED",
-    -9: "FFT_E_ARG",
+    -9: "FFT_E_ARG", -10: "FFT_E_CAPACITY",
 }
 EXPORTED = [
     "fft_plan_create", "fft_plan_create_ex", "fft_execute", "fft_plan_destroy",
     "fft_strerror", "fft_plan_get_info", "fft_plan_set_timing", "fft_plan_read_timing",
     "fft_abi_version", "fft_plan_create_many", "fft_plan_create_tuned", "fft_plan_set_precision",
-    "fft_plan_create_paper",
+    "fft_plan_create_paper", "fft_execute_static",
 ]
 
 
@@ -126,6 +126,7 @@ def lib():
             L.fft_plan_create_paper.argtypes = [i64, i64, i32, ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.POINTER(vp)]
             L.fft_execute.argtypes = [vp, vp, vp, i32, vp]
+            L.fft_execute_static.argtypes = [i64, i64, i32, vp, vp, i32, vp]
             L.fft_plan_destroy.argtypes = [vp]
             L.fft_strerror.argtypes = [i32]
             L.fft_strerror.restype = ctypes.c_char_p
@@ -137,7 +138,7 @@ def lib():
             for name in ("fft_plan_create", "fft_plan_create_ex", "fft_plan_create_many", "fft_plan_create_paper",
                          "fft_plan_create_tuned", "fft_plan_set_precision", "fft_execute",
                          "fft_plan_destroy", "fft_plan_get_info", "fft_plan_set_timing",
-                         "fft_plan_read_timing", "fft_abi_version"):
+                         "fft_plan_read_timing", "fft_abi_version", "fft_execute_static"):
                 getattr(L, name).restype = i32
             _lib = L
     return _lib

@@ -1467,6 +1467,28 @@ int shape_plan(fft_plan *p, int64_t n, int64_t batch, int dtype, const fft_plan_
     return FFT_OK;
 }
 
+// Scratch of the allocation-free entry point fft_execute_static: the
+// inter-pass array (up to STATIC_SCRATCH_BYTES) followed by the weight
+// tables (up to STATIC_TABLE_BYTES).  Each GPU the library runs on holds its
+// own copy until the process ends; every call on that GPU shares it.  In host
+// code the array's name is only a stand-in: kernels get the device address
+// that hipGetSymbolAddress returns for the current device (StaticDevice).
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(32) << 20;
+constexpr size_t STATIC_TABLE_BYTES = size_t(256) << 10;
+__device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES + STATIC_TABLE_BYTES];
+
+// Per device: the address of `scratch` there, and which transform's tables
+// the array holds (the last call's, in host order).
+struct StaticDevice {
+    bool ready = false;
+    unsigned char *ptr = nullptr;
+    int64_t table_n = 0;
+    int table_dtype = -1;
+};
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex static_mutex;
+StaticDevice static_devices[STATIC_MAX_DEVICES];
+
 } // namespace
 
 extern "C" {
@@ -1485,6 +1507,7 @@ const char *fft_strerror(int code) {
     case FFT_E_HIP: return "HIP runtime call or kernel launch failed";
     case FFT_E_UNSUPPORTED: return "valid request outside what the library supports";
     case FFT_E_ARG: return "invalid option";
+    case FFT_E_CAPACITY: return "request exceeds the fixed scratch of fft_execute_static";
     default: return "unknown status code";
     }
 }
@@ -1996,6 +2019,44 @@ int fft_execute(const fft_plan *plan, const void *in, void *out, int sign, void 
     if (cur != p->device && hipSetDevice(p->device) != hipSuccess) return FFT_E_HIP;
     const int rc = launch_plan(p, in, out, sign, st);
     if (cur != p->device) (void)hipSetDevice(cur);
+    return rc;
+}
+
+int fft_execute_static(int64_t n, int64_t batch, int dtype, const void *in, void *out, int sign, void *stream) {
+    // The plan lives on the stack and owns no device memory: its scratch
+    // array and tables point into this device's `scratch`.
+    fft_plan p;
+    int rc = shape_plan(&p, n, batch, dtype, nullptr);
+    if (rc != FFT_OK) return rc;
+    if (p.scratch_bytes > STATIC_SCRATCH_BYTES || p.table_bytes > STATIC_TABLE_BYTES) return FFT_E_CAPACITY;
+    rc = check_execute(in, out, sign, p.esize, p.total);
+    if (rc != FFT_OK) return rc;
+    if (p.device < 0 || p.device >= STATIC_MAX_DEVICES) return FFT_E_UNSUPPORTED;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> g(static_mutex);
+    StaticDevice &d = static_devices[p.device];
+    if (!d.ready) { // once per device, with that device current (shape_plan took the current one)
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return FFT_E_HIP;
+        }
+        d.ptr = static_cast<unsigned char *>(ptr);
+        d.ready = true;
+    }
+    p.scratch = p.scratch_bytes ? d.ptr : nullptr;
+    p.tables = d.ptr + STATIC_SCRATCH_BYTES;
+    const bool regenerate = d.table_n != n || d.table_dtype != dtype;
+    rc = fill_tables(&p, st, regenerate);
+    if (rc == FFT_OK && regenerate) {
+        d.table_n = n;
+        d.table_dtype = dtype;
+    } else if (rc != FFT_OK) {
+        d.table_n = 0; // contents unknown: regenerate next time
+        d.table_dtype = -1;
+    }
+    if (rc == FFT_OK) rc = launch_plan(&p, in, out, sign, st);
+    p.scratch = p.tables = nullptr;
     return rc;
 }
 

@@ -51,7 +51,7 @@ def test_abi_version():
 
 def test_strerror_covers_codes():
     L = _lib()
-    for code in range(-9, 1):
+    for code in range(-10, 1):
         s = L.fft_strerror(code)
         assert s and s != b"unknown status code", code
     assert L.fft_strerror(-1234) == b"unknown status code"
