@@ -130,6 +130,34 @@ def summarize_counters(fetch_csv: str, write_csv: str, log2n: int, out_path: str
     return rec
 
 
+def host_facts() -> dict:
+    """CPU model and core counts of the host the oracle legs run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count() or 1, "affinity": affinity}
+
+
+def oracle_threads() -> int:
+    """Threads for the batched oracle legs: this process's CPU share
+    (OMP_NUM_THREADS when set, else the affinity mask), at most 16."""
+    try:
+        t = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        t = 0
+    return max(1, min(16, t or host_facts()["affinity"]))
+
+
 def cpu_baseline(x0, x1, y0_gpu, y1_gpu):
     """The FP64 oracle (untuned, one thread) on one forward and one inverse
     transform of the benchmark's own inputs; also returns the parity of the
@@ -147,9 +175,124 @@ def cpu_baseline(x0, x1, y0_gpu, y1_gpu):
             "sample": "one forward + one inverse c64 n=2^%d transform (FP64 recursive radix-2, "
                       "1 thread), %.2f s" % (int(math.log2(n)), dt),
             "seconds": round(dt, 3)}
+    base.update(host_facts())
     parity = {"rel_l2_forward": oracle.rel_l2(y0_gpu, r0), "rel_l2_inverse": oracle.rel_l2(y1_gpu, r1),
               "tolerance": 1e-6}
     return base, parity
+
+
+def measure_config1(torch, lf, datagen, reps: int = 100):
+    """Config 1: one n = 2^10 complex128 transform (U[-1,1], seed 1, sign -1)
+    lifted 32 x 32 with radix-2 stages in both passes; latency-bound, so
+    microseconds per transform over back-to-back executes."""
+    import numpy as np
+    x_np = datagen.signals(1024, 1, np.complex128, "uniform", 1)
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(x_np).to(dev)
+    y = torch.empty_like(x)
+    plan = lf.Plan(1024, 1, torch.complex128, log2_p=5, radix=2)
+    for _ in range(5):
+        plan.execute(x, y, -1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.execute(x, y, -1)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / reps * 1e3
+    plan.destroy()
+    out = {"workload": "c128 n=2^10, U[-1,1] seed 1, forward, lift 32 x 32, radix-2 stages",
+           "us_per_transform": round(us, 2), "gflops": round(5.0 * 1024 * 10 / (us * 1e-6) / 1e9, 3)}
+    return out, (x_np[0], y.cpu().numpy()[0])
+
+
+def oracle_leg_config1(keep, reps: int = 200) -> dict:
+    import numpy as np
+
+    import oracle
+    x0, y0 = keep
+    xb = x0.astype(np.complex128)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ref = oracle.fft(xb, -1)
+    dt = (time.perf_counter() - t0) / reps
+    return {"sample": "the config-1 transform, %d repetitions" % reps, "threads": 1,
+            "us_per_transform": round(dt * 1e6, 2), "rel_l2_gpu_vs_oracle": float("%.3g" % oracle.rel_l2(y0, ref)),
+            "tolerance": 1e-12}
+
+
+def oracle_leg_config3(keep, threads: int) -> dict:
+    """All 4096 transforms of config 3 through the oracle, one batched call
+    per length class on `threads` threads; the packed GPU output's largest
+    per-transform relative L2 and the global one."""
+    import numpy as np
+
+    import oracle
+    x_np, y_np, lengths = keep
+    offs = np.concatenate([[0], np.cumsum(lengths)[:-1]])
+    classes = {}
+    for i, ln in enumerate(lengths):
+        classes.setdefault(ln, []).append(i)
+    worst, num, den, secs = 0.0, 0.0, 0.0, 0.0
+    for ln, idx in classes.items():
+        X = np.stack([x_np[offs[i]:offs[i] + ln] for i in idx]).astype(np.complex128)
+        t0 = time.perf_counter()
+        R = oracle.fft_batch(X, -1, threads=threads)
+        secs += time.perf_counter() - t0
+        for r, i in zip(R, idx):
+            g = y_np[offs[i]:offs[i] + ln].astype(np.complex128)
+            d = float(np.sum(np.abs(g - r) ** 2))
+            e = float(np.sum(np.abs(r) ** 2))
+            worst = max(worst, math.sqrt(d / e))
+            num += d
+            den += e
+    flops = sum(5.0 * ln * math.log2(ln) for ln in lengths)
+    return {"sample": "all 4096 transforms", "threads": threads, "seconds": round(secs, 3),
+            "gflops": round(flops / secs / 1e9, 3), "max_rel_l2": float("%.3g" % worst),
+            "global_rel_l2": float("%.3g" % math.sqrt(num / den)), "tolerance": 1e-6}
+
+
+def oracle_leg_config5(keep, threads: int, coords: int = 64, h: float = 1e-3) -> dict:
+    """Config 5 in FP64 on the host: the reference gradient 2 F^H(w . F x) of
+    L = sum w |F x|^2 through the oracle (`threads` threads), against the GPU
+    autograd gradient; and central differences with step h at `coords`
+    seeded coordinates, each from two full evaluations of L (L is quadratic,
+    so the central difference has no truncation error)."""
+    import numpy as np
+
+    import oracle
+    x, w, g_gpu = keep
+    batch, n = x.shape
+    xb = x.astype(np.complex128)
+    t0 = time.perf_counter()
+    y = oracle.fft_batch(xb, -1, threads=threads)
+    gref = 2.0 * oracle.fft_batch(w * y, 1, threads=threads)
+    secs = time.perf_counter() - t0
+    grad_err = max(oracle.rel_l2(g_gpu[b], gref[b]) for b in range(batch))
+    rng = np.random.default_rng(np.random.SeedSequence([5, 0xFD]))
+    picks = [(int(rng.integers(batch)), int(rng.integers(n))) for _ in range(coords)]
+    k = np.arange(n, dtype=np.int64)
+    fd_err_gpu, fd_err_ref = 0.0, 0.0
+    scale = float(np.abs(gref).max())
+    t1 = time.perf_counter()
+    for b, j in picks:
+        c = np.exp(-2j * np.pi * ((j * k) % n) / n)  # column j of F (sign -1)
+        def loss(delta):
+            return float(np.sum(w[b] * np.abs(y[b] + delta * c) ** 2))
+        d_re = (loss(h) - loss(-h)) / (2 * h)
+        d_im = (loss(1j * h) - loss(-1j * h)) / (2 * h)
+        fd = d_re + 1j * d_im  # conjugate Wirtinger gradient, PyTorch's convention
+        fd_err_gpu = max(fd_err_gpu, abs(fd - complex(g_gpu[b, j])) / scale)
+        fd_err_ref = max(fd_err_ref, abs(fd - gref[b, j]) / scale)
+    fd_secs = time.perf_counter() - t1
+    flops = 2 * 5.0 * n * math.log2(n) * batch
+    return {"sample": "all 8 signals; %d coordinates for central differences" % coords, "threads": threads,
+            "seconds_reference_gradient": round(secs, 3), "gflops": round(flops / secs / 1e9, 3),
+            "seconds_central_differences": round(fd_secs, 3),
+            "grad_rel_l2_gpu_vs_oracle": float("%.3g" % grad_err),
+            "fd_max_err_gpu": float("%.3g" % fd_err_gpu), "fd_max_err_oracle": float("%.3g" % fd_err_ref),
+            "fd_err_unit": "largest |difference| over the coordinates / largest |reference gradient|"}
 
 
 def measure_fwd_bwd(torch, lf, datagen, reps: int = 5) -> dict:
@@ -195,13 +338,19 @@ def measure_fwd_bwd(torch, lf, datagen, reps: int = 5) -> dict:
     plan.set_timing(False)
     fft_ms_plain = (kms[0] + kms[1]) / reps
     flops = 2 * 5.0 * n * math.log2(n) * batch
+    # one more step, keeping its gradient for the oracle leg
+    y = lf.LiftFFT.apply(x, -1)
+    (w * (y.real * y.real + y.imag * y.imag)).sum().backward()
+    torch.cuda.synchronize()
+    keep = (x.detach().cpu().numpy(), w.cpu().numpy().astype(np.float64), x.grad.cpu().numpy())
+    x.grad = None
     return {"workload": "c64 batch 8 x n=2^22, loss sum w|Fx|^2, forward + adjoint backward",
             "ms_step_total": round(ms_step, 4),
             "ms_two_ffts_in_autograd": round(fft_ms_ad, 4),
             "ms_two_plain_executes": round(fft_ms_plain, 4),
             "ratio_vs_plain": round(fft_ms_ad / fft_ms_plain, 4),
             "gflops_ffts": round(flops / (fft_ms_ad * 1e-3) / 1e9, 1),
-            "hbm_gbps_ffts": round(2 * 32 * n * batch / (fft_ms_ad * 1e-3) / 1e9, 1)}
+            "hbm_gbps_ffts": round(2 * 32 * n * batch / (fft_ms_ad * 1e-3) / 1e9, 1)}, keep
 
 
 def measure_ragged(torch, lf, datagen, reps: int = 10) -> dict:
@@ -236,6 +385,11 @@ def measure_ragged(torch, lf, datagen, reps: int = 10) -> dict:
         info = plan.info()
         plan.destroy()
     ms_direct, ms_graph = ms_mode[False], ms_mode[True]
+    plan = lf.Plan.uneven(lengths, torch.complex64)
+    plan.execute(xs[0], ys[0], -1)
+    torch.cuda.synchronize()
+    plan.destroy()
+    keep = (x_np, ys[0].cpu().numpy(), lengths)
 
     # (a) per-class batched plans on contiguous class buffers.
     offs = np.concatenate([[0], np.cumsum(lengths)[:-1]])
@@ -285,7 +439,7 @@ def measure_ragged(torch, lf, datagen, reps: int = 10) -> dict:
             "ms_one_launch_per_transform": round(ms_each, 4),
             "speedup_vs_per_class": round(ms_classes / ms_direct, 3),
             "speedup_vs_per_transform": round(ms_each / ms_direct, 3),
-            "grid": [info["grid_pass1"], info["grid_pass2"]]}
+            "grid": [info["grid_pass1"], info["grid_pass2"]]}, keep
 
 
 def measure_precision(torch, lf, datagen, reps: int = 5):
@@ -322,23 +476,36 @@ def measure_precision(torch, lf, datagen, reps: int = 5):
             y32 = y.clone()
         diff = float(torch.linalg.vector_norm((y - y32).to(torch.complex128)) /
                      torch.linalg.vector_norm(y32.to(torch.complex128)))
-        firsts[mode] = y[0].cpu().numpy()
+        firsts[mode] = y[:PRECISION_SUBSET].cpu().numpy()
         out[mode] = {"ms": round(ms, 4), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
                      "hbm_gbps_algorithmic": round(32 * n * batch / (ms * 1e-3) / 1e9, 1),
                      "rel_l2_vs_fp32_path": float("%.3g" % diff)}
     plan.destroy()
     del y32
-    return out, (x_np[0], firsts)
+    return out, (x_np[:PRECISION_SUBSET], firsts)
 
 
-def precision_oracle_errors(x0, firsts):
-    """CPU-baseline leg: relative L2 of each precision form's transform 0
-    against the FP64 oracle."""
+PRECISION_SUBSET = 16  # transforms of config 4 checked against the oracle
+
+
+def precision_oracle_errors(x_sub, firsts, threads):
+    """CPU leg of config 4: the oracle on the first PRECISION_SUBSET
+    transforms (nproc threads); each precision form's largest relative L2
+    over them."""
     import numpy as np
 
     import oracle
-    ref = oracle.fft(x0.astype(np.complex128), -1)
-    return {mode: float("%.3g" % oracle.rel_l2(y, ref)) for mode, y in firsts.items()}
+    t0 = time.perf_counter()
+    ref = oracle.fft_batch(x_sub.astype(np.complex128), -1, threads=threads)
+    dt = time.perf_counter() - t0
+    n = x_sub.shape[1]
+    errs = {mode: float("%.3g" % max(oracle.rel_l2(y[b], ref[b]) for b in range(len(ref))))
+            for mode, y in firsts.items()}
+    flops = 5.0 * n * math.log2(n) * len(ref)
+    leg = {"sample": "%d of the 256 transforms of 2^20 (the first, seed 4)" % len(ref), "threads": threads,
+           "seconds": round(dt, 3), "gflops": round(flops / dt / 1e9, 3),
+           "max_rel_l2_vs_oracle": errs}
+    return errs, leg
 
 
 def measure_three_level(torch, lf, xs, S, steps, warmup, stream, n):
@@ -391,6 +558,12 @@ def measure_three_level(torch, lf, xs, S, steps, warmup, stream, n):
         "lines_per_block": [info["lines_per_block_pass1"], info["lines_per_block_pass2"],
                             info["lines_per_block_pass3"]],
         "alg_bytes_per_step": 2 * 3 * bytes_per_launch,
+        # the transform against the two-pass method's 32 n bytes (the
+        # roofline below counts each of the three passes' own 16 n bytes)
+        "per_transform": {"us": round(ms_step / 2 * 1e3, 2),
+                          "gbps_on_32n_bytes": round(4 * n * esize / (ms_step / 2 * 1e-3) / 1e9, 1),
+                          "frac_of_peak_on_32n_bytes": round(4 * n * esize / (ms_step / 2 * 1e-3) / 1e9
+                                                             / HBM_PEAK_GBS, 4)},
         "roofline": {
             "bound": "hbm",
             "kernel": "axis",
@@ -408,6 +581,96 @@ def measure_three_level(torch, lf, xs, S, steps, warmup, stream, n):
     }
 
 
+def run_sweep(torch, lf, log2n: int, sets: int = 4, reps: int = 12) -> int:
+    """Per-pass kernel times of the plan configurations at one length (c64,
+    N(0,1) inputs over rotating buffer sets, forward and inverse alternating,
+    per-kernel HIP events), with streaming references over the same bytes:
+    the numbers behind the tile-width, kernel-variant and lift comparisons.
+    One JSON object per line."""
+    from paper_0811_2535_amd import binding as B
+    n = 1 << log2n
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(2)
+    xs = [torch.randn(n, dtype=torch.complex64, device=dev, generator=gen) for _ in range(sets)]
+    ys = [torch.empty_like(x) for x in xs]
+    st = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timeit(fn):
+        for i in range(3):
+            fn(i)
+        torch.cuda.synchronize()
+        e0.record(st)
+        for i in range(reps):
+            fn(i)
+        e1.record(st)
+        torch.cuda.synchronize()
+        return round(e0.elapsed_time(e1) / reps * 1e3, 1)
+
+    def emit(rec):
+        print(json.dumps(rec), flush=True)
+
+    emit({"reference": "torch.neg, rotating buffers (8n bytes read + 8n written)",
+          "us": timeit(lambda i: torch.neg(xs[(i + 1) % sets], out=ys[i % sets]))})
+    emit({"reference": "torch copy_, rotating buffers", "us": timeit(lambda i: ys[i % sets].copy_(xs[(i + 1) % sets]))})
+    emit({"reference": "torch.neg, same buffers every time (last-level cache warm)",
+          "us": timeit(lambda i: torch.neg(xs[0], out=ys[0]))})
+    tmp = torch.empty_like(xs[0])
+
+    def chain(i):
+        torch.neg(xs[(i + 1) % sets], out=ys[i % sets])
+        torch.neg(ys[i % sets], out=tmp)
+    emit({"reference": "two torch.neg in a chain, the second reading what the first wrote", "us": timeit(chain)})
+
+    def plan_times(label, **kw):
+        try:
+            p = lf.Plan(n, 1, torch.complex64, **kw)
+        except B.FFTError as ex:
+            emit({"config": label, "unsupported": ex.name})
+            return
+        info = p.info()
+        for i in range(3):
+            p.execute(xs[i % sets], ys[i % sets], -1, st)
+        torch.cuda.synchronize()
+        p.set_timing(True)
+        p.read_timing(reset=True)
+        for i in range(reps):
+            p.execute(xs[i % sets], ys[i % sets], -1 if i % 2 == 0 else 1, st)
+        ms, cnt = p.read_timing(reset=True)
+        p.set_timing(False)
+        p.destroy()
+        per = [round(ms[k] / cnt[k] * 1e3, 1) for k in range(3) if cnt[k]]
+        emit({"config": label, "us_per_pass": per, "us_total": round(sum(per), 1),
+              "lines_per_block": [info["lines_per_block_pass1"], info["lines_per_block_pass2"]],
+              "threads": [info["threads_pass1"], info["threads_pass2"]],
+              "lds": [info["lds_bytes_pass1"], info["lds_bytes_pass2"]],
+              "variants": [info["variant_pass1"], info["variant_pass2"]]})
+
+    TWO, THREE = B.FFT_OPT_TWO_LEVEL, B.FFT_OPT_THREE_LEVEL
+    SPLIT, FULL = B.FFT_OPT_SPLIT_EXCHANGE, B.FFT_OPT_FULL_EXCHANGE
+    plan_times("two-level default", flags=TWO)
+    plan_times("three-level default", flags=THREE)
+    plan_times("three-level shuffle exchange", flags=THREE | B.FFT_OPT_SHUFFLE_EXCHANGE)
+    plan_times("three-level split exchange", flags=THREE | SPLIT)
+    plan_times("three-level 32 lines", flags=THREE, lines_per_block=32)
+    for T1 in (1, 2, 4, 8):
+        for vpt in (16, 32):
+            for fl, fn in ((SPLIT, "split"), (FULL, "complex")):
+                plan_times("pass 1 T=%d, %d values/thread, %s exchange" % (T1, vpt, fn), flags=TWO | fl,
+                           lines_per_block=T1, lines_per_block2=4, values_per_thread=vpt, values_per_thread2=16)
+    for T2 in (2, 4, 8):
+        for vpt in (16, 32):
+            for fl, fn in ((SPLIT, "split"), (FULL, "complex")):
+                plan_times("pass 2 T=%d, %d values/thread, %s exchange" % (T2, vpt, fn), flags=TWO | fl,
+                           lines_per_block=2, lines_per_block2=T2, values_per_thread=16, values_per_thread2=vpt)
+    for flags, fn in ((B.FFT_OPT_PERSISTENT, "persistent"), (B.FFT_OPT_DENSE | SPLIT, "dense split")):
+        plan_times("two-level %s" % fn, flags=TWO | flags)
+    for lp in (10, 11, 13, 14):
+        plan_times("two-level split p = 2^%d" % lp, flags=TWO, log2_p=lp)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -422,6 +685,10 @@ def main() -> int:
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary from two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of this benchmark and exit")
+    ap.add_argument("--sweep", action="store_true",
+                    help="print per-pass kernel times of the plan configurations (tile widths, "
+                         "kernel variants, lifts) with streaming references, one JSON object per "
+                         "line, and exit")
     ap.add_argument("--copy-reps", type=int, default=10,
                     help="device-to-device copies of one pass's bytes, timed for context and "
                          "used as the known-size reference kernel for HBM counters")
@@ -452,6 +719,8 @@ def main() -> int:
     lf.lib()  # fail loudly if the HIP library is missing
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.sweep:
+        return run_sweep(torch, lf, args.log2n)
     n = 1 << args.log2n
     S = max(2, args.sets)
 
@@ -589,14 +858,16 @@ def main() -> int:
         "wall_s": round(wall, 4),
         "three_level": three,
     }
-    precision_firsts = None
+    precision_firsts = keep1 = keep3 = keep5 = None
     if not args.no_extras:
+        print("[bench] config 1: n=2^10 complex128", file=sys.stderr, flush=True)
+        result["config1"], keep1 = measure_config1(torch, lf, datagen)
         print("[bench] forward + adjoint backward, batch 8 x 2^22", file=sys.stderr, flush=True)
         del xs, ys
-        result["fwd_bwd"] = measure_fwd_bwd(torch, lf, datagen)
+        result["fwd_bwd"], keep5 = measure_fwd_bwd(torch, lf, datagen)
         lf.clear_plan_cache()
         print("[bench] batched uneven lengths, 4096 transforms", file=sys.stderr, flush=True)
-        result["ragged"] = measure_ragged(torch, lf, datagen)
+        result["ragged"], keep3 = measure_ragged(torch, lf, datagen)
         print("[bench] precision forms, 256 x 2^20", file=sys.stderr, flush=True)
         result["precision"], precision_firsts = measure_precision(torch, lf, datagen)
         print("[bench] autotuner on the headline shape", file=sys.stderr, flush=True)
@@ -611,10 +882,25 @@ def main() -> int:
         base, parity = cpu_baseline(host_inputs[0], host_inputs[1], y0, y1)
         result["cpu_baseline"] = base
         result["parity"] = parity
+        threads = oracle_threads()
+        legs = {}
+        if keep1 is not None:
+            legs["config1"] = oracle_leg_config1(keep1)
+        if keep3 is not None:
+            print("[bench] oracle leg, config 3 (%d threads)" % threads, file=sys.stderr, flush=True)
+            legs["config3"] = oracle_leg_config3(keep3, threads)
+            result["ragged"]["max_rel_l2_vs_oracle"] = legs["config3"]["max_rel_l2"]
         if precision_firsts is not None:
-            errs = precision_oracle_errors(*precision_firsts)
+            print("[bench] oracle leg, config 4 (%d threads)" % threads, file=sys.stderr, flush=True)
+            errs, legs["config4"] = precision_oracle_errors(*precision_firsts, threads)
             for mode, e in errs.items():
-                result["precision"][mode]["rel_l2_transform0_vs_oracle"] = e
+                result["precision"][mode]["max_rel_l2_vs_oracle_subset"] = e
+        if keep5 is not None:
+            print("[bench] oracle leg, config 5 (%d threads)" % threads, file=sys.stderr, flush=True)
+            legs["config5"] = oracle_leg_config5(keep5, threads)
+            result["fwd_bwd"]["grad_rel_l2_vs_oracle"] = legs["config5"]["grad_rel_l2_gpu_vs_oracle"]
+        if legs:
+            result["cpu_oracle_legs"] = legs
     plan.destroy()
     print(json.dumps(result), flush=True)
     return 0

@@ -118,6 +118,14 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out);
  *                     (three levels from n = 2^24 on, radix 16 and default
  *                     kernels, unless a two-level option or lines_per_block
  *                     is given).
+ *                     FFT_OPT_SHUFFLE_EXCHANGE (with FFT_OPT_THREE_LEVEL
+ *                     only): axis passes over 256-point complex64 lines
+ *                     exchange data between their two stages by wavefront
+ *                     shuffles within 16-lane rows (DPP and ds_swizzle)
+ *                     instead of the LDS tile (passes over other lengths
+ *                     keep the default kernel; FFT_E_UNSUPPORTED when no
+ *                     pass has 256-point lines or the type is complex128;
+ *                     other kernel-variant options: FFT_E_ARG).
  *                     FFT_OPT_THREE_LEVEL takes no two-level options
  *                     (log2_p, lines_per_block2, values_per_thread2,
  *                     scratch_width: FFT_E_ARG); lines_per_block then sets
@@ -158,7 +166,8 @@ enum {
     FFT_OPT_ONE_TILE = 16,
     FFT_OPT_DENSE = 32,
     FFT_OPT_TWO_LEVEL = 128,
-    FFT_OPT_THREE_LEVEL = 256
+    FFT_OPT_THREE_LEVEL = 256,
+    FFT_OPT_SHUFFLE_EXCHANGE = 512
 };
 typedef struct fft_plan_opts {
     int32_t log2_p;
@@ -288,7 +297,8 @@ const char *fft_strerror(int code);
  *   scratch_bytes, table_bytes device memory the plan owns
  *   variant_pass1/2            kernel variant bits: 1 = 32 values per
  *                              thread, 2 = split exchange, 4 = persistent,
- *                              8 = dense (64-VGPR cap)
+ *                              8 = dense (64-VGPR cap), 16/32 = the
+ *                              matrix-core forms, 64 = shuffle exchange
  *   precision                  FFT_PREC_* set by fft_plan_set_precision
  *   length_classes, graph_launch  plans of uneven lengths: number of
  *                              distinct lengths, and whether executes replay
@@ -337,7 +347,10 @@ int fft_plan_get_info(const fft_plan *plan, fft_plan_info *info);
  * points (n = 2^24), each stage radix 16, with radix 16, 16 values per
  * thread and one tile per workgroup; otherwise FFT_E_UNSUPPORTED and the
  * plan is unchanged.
- * FFT_E_ARG for an unknown mode.  Takes effect for later executes.
+ * FFT_E_ARG for an unknown mode.  Takes effect for later executes.  The
+ * first switch to a matrix-core form allocates a 4 KB table of the DFT
+ * matrix in that form's operand layout (hi and lo parts from FP64 angles)
+ * and fills it synchronously; FFT_E_OOM / FFT_E_HIP if that fails.
  */
 enum { FFT_PREC_FP32 = 0, FFT_PREC_F16X2 = 1, FFT_PREC_BF16X2 = 2 };
 int fft_plan_set_precision(fft_plan *plan, int mode);
@@ -362,8 +375,10 @@ int fft_plan_read_timing(fft_plan *plan, double ms_out[3], int64_t launches_out[
  * two-level default, other lifts n = p*q and the single/two-pass threshold,
  * radix 2, the pass-kernel variants and tile widths, each naming its lift
  * with FFT_OPT_TWO_LEVEL or FFT_OPT_THREE_LEVEL -- each timed on device
- * buffers the call allocates (forward
- * executes on a private stream, about 2 ms of work each) and checked
+ * buffers the call allocates (forward executes on a private stream, about
+ * 2 ms of work each, rotating over three input/output buffer sets while a
+ * buffer is below 512 MB so that no execute reads an input the last-level
+ * cache still holds) and checked
  * against the default plan's output (a configuration whose output differs
  * by more than 1e-4 (complex64) or 1e-10 (complex128) of the largest output
  * is never chosen).  Returns the fastest as *plan_out; if result is not

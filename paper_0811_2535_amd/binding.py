@@ -53,6 +53,7 @@ FFT_OPT_DENSE = 32
 FFT_OPT_GRAPH = 64
 FFT_OPT_TWO_LEVEL = 128
 FFT_OPT_THREE_LEVEL = 256
+FFT_OPT_SHUFFLE_EXCHANGE = 512
 
 
 class PlanOpts(ctypes.Structure):
@@ -297,21 +298,26 @@ class Plan:
 
 
 _plans: dict = {}
+_plans_lock = threading.Lock()
 
 
 def cached_plan(n: int, batch: int, dtype, device: torch.device, stream=None) -> Plan:
-    """One plan per (n, batch, dtype, device, stream, host thread), created on
-    first use.  A plan's executes share its scratch array, so they must be
-    ordered on one stream; keying the cache on the stream and the calling
-    thread gives work on different streams (or threads) plans of their own."""
+    """One plan per (n, batch, dtype, device, stream), created on first use.
+    A plan's executes share its scratch array, so they must be ordered on one
+    stream: work on another stream gets a plan of its own.  Host threads that
+    share a stream (the autograd engine runs backward on a thread of its own,
+    on the forward's stream) share the plan; :func:`fft` serialises their
+    execute calls with the plan's lock."""
     if stream is None:
         stream = torch.cuda.current_stream(device)
-    key = (int(n), int(batch), dtype, device.index, int(stream.cuda_stream), threading.get_ident())
-    p = _plans.get(key)
-    if p is None:
-        with torch.cuda.device(device):
-            p = Plan(n, batch, dtype)
-        _plans[key] = p
+    key = (int(n), int(batch), dtype, device.index, int(stream.cuda_stream))
+    with _plans_lock:
+        p = _plans.get(key)
+        if p is None:
+            with torch.cuda.device(device):
+                p = Plan(n, batch, dtype)
+            p.lock = threading.Lock()
+            _plans[key] = p
     return p
 
 
@@ -338,5 +344,6 @@ def fft(x: torch.Tensor, sign: int = -1, out: torch.Tensor | None = None) -> tor
         return out
     stream = torch.cuda.current_stream(x.device)
     plan = cached_plan(n, batch, x.dtype, x.device, stream)
-    plan.execute(x, out, sign, stream)
+    with plan.lock:
+        plan.execute(x, out, sign, stream)
     return out

@@ -271,18 +271,19 @@ __device__ __forceinline__ double2 buf_load(const double2 *, rsrc_t r, uint32_t 
 template <int AUX = 0> __device__ __forceinline__ void buf_store(float2 v, rsrc_t r, uint32_t voff, uint32_t soff) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, AUX);
 }
-// A 16-byte element is stored as two 8-byte stores: with a single 16-byte
-// buffer store, the compiler here lets the next VALU instruction overwrite
-// the store's first data register without a wait state, and the stored
-// first dword then intermittently holds the new value.
-// (The empty asm statement keeps the two stores from being merged back.)
+// A 16-byte element is stored as two 8-byte stores.  Single 16-byte buffer
+// stores of complex128 results gave, intermittently (about one transform in
+// 200), an element whose first dword held another value; with two 8-byte
+// stores no such element has been seen (repeat runs are checked bit for
+// bit).  What caused it was not established.  (The empty asm statement
+// keeps the two stores from being merged back.)
 template <int AUX = 0> __device__ __forceinline__ void buf_store(double2 v, rsrc_t r, uint32_t voff, uint32_t soff) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v.x), r, voff, soff, AUX);
     __asm__ volatile("" ::: "memory");
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v.y), r, voff + 8, soff, AUX);
 }
 // Plain global store of one element (transforms addressed in 64 bits);
-// complex128 as two 8-byte stores, for the reason given above.
+// complex128 as two 8-byte stores, as above.
 __device__ __forceinline__ void global_store(float2 *p, float2 v) { *p = v; }
 __device__ __forceinline__ void global_store(double2 *p, double2 v) {
     double *q = reinterpret_cast<double *>(p);
@@ -411,6 +412,42 @@ __device__ __forceinline__ void run_stages(C *v, void *line_base, const C *twl, 
 }
 
 // ---------------------------------------------------------------------------
+// Wavefront shuffles.  A 16 x 16 transpose across the 16 lanes of one DPP row
+// (lanes 16k .. 16k+15): on entry lane j holds row j of a matrix M in
+// v[0..16), on exit v[r] = M[r][j].  Four butterfly steps d = 1, 2, 4, 8; in
+// step d, lanes j and j^d swap the eight entries whose register index
+// differs from the lane index in bit d (lane j sends v[r | d] if bit d of j
+// is clear, v[r] if it is set, and stores what it receives in the other
+// slot).  Lane exchanges: DPP quad permutations for d = 1, 2, ds_swizzle
+// (bit-mask mode, xor within 32 lanes) for d = 4, 8 -- no LDS storage and no
+// barrier.
+template <int D> __device__ __forceinline__ float xor_lanes(float x) {
+    const int i = __builtin_bit_cast(int, x);
+    if constexpr (D == 1) return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(i, 0xB1, 0xF, 0xF, false));
+    else if constexpr (D == 2) return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(i, 0x4E, 0xF, 0xF, false));
+    else if constexpr (D == 4) return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(i, 0x101F));
+    else return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(i, 0x201F));
+}
+template <int D, typename C> __device__ __forceinline__ void transpose_step(C *v, int j) {
+    const bool hi = (j & D) != 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        if (r & D) continue;
+        const int s = r | D;
+        const C send = hi ? v[r] : v[s];
+        const C recv = mk<C>(xor_lanes<D>(send.x), xor_lanes<D>(send.y));
+        if (hi) v[r] = recv;
+        else v[s] = recv;
+    }
+}
+template <typename C> __device__ __forceinline__ void transpose16_row(C *v, int j) {
+    transpose_step<1>(v, j);
+    transpose_step<2>(v, j);
+    transpose_step<4>(v, j);
+    transpose_step<8>(v, j);
+}
+
+// ---------------------------------------------------------------------------
 // Precision forms on the matrix cores.  A radix-16 stage is, per group of 16
 // butterflies, the product of the 16 x 16 DFT matrix with a 16 x 16 block of
 // inputs.  With complex numbers split into real and imaginary rows this is
@@ -467,25 +504,44 @@ __device__ __forceinline__ void split_hilo(const float *x, typename MfmaOps<PREC
 }
 
 // This lane's share of the two DFT-matrix operands (forward sign), split
-// into hi and lo parts: row m = l % 16, columns k = 8(l/16) + i.
+// into hi and lo parts: row m = l % 16, columns k = 8(l/16) + i.  The plan
+// generates them once (dft_operand_table, FP64 angles rounded once to FP32,
+// then split) and every workgroup loads its lanes' 64 bytes.
 template <int PREC> struct DftOperands {
-    typename MfmaOps<PREC>::V rh, rl, ih, il;
-    __device__ __forceinline__ explicit DftOperands(int lane) {
-        float ar[8], ai[8];
-        const int m = lane & 15;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int k = 8 * (lane >> 4) + i, r = k & 15, e = (m * r) & 15;
-            double sn, cs;
-            sincospi(double(e) / 8.0, &sn, &cs); // angle 2*pi*e/16
-            // F[m][r] = cos - i sin;  Yr = sum cos Xr + sin Xi;  Yi = sum -sin Xr + cos Xi
-            ar[i] = float(k < 16 ? cs : sn);
-            ai[i] = float(k < 16 ? -sn : cs);
-        }
-        split_hilo<PREC>(ar, rh, rl);
-        split_hilo<PREC>(ai, ih, il);
+    using V = typename MfmaOps<PREC>::V;
+    V rh, rl, ih, il;
+    __device__ __forceinline__ DftOperands(int lane, const void *table) {
+        const V *t = static_cast<const V *>(table) + 4 * lane;
+        rh = t[0];
+        rl = t[1];
+        ih = t[2];
+        il = t[3];
     }
 };
+
+// The operand table: entry 4*l + {0, 1, 2, 3} = lane l's {rh, rl, ih, il}.
+// One wavefront of 64 threads.
+template <int PREC> __global__ void dft_operand_table(typename MfmaOps<PREC>::V *out) {
+    const int lane = threadIdx.x & 63;
+    float ar[8], ai[8];
+    const int m = lane & 15;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int k = 8 * (lane >> 4) + i, r = k & 15, e = (m * r) & 15;
+        double sn, cs;
+        sincospi(double(e) / 8.0, &sn, &cs); // angle 2*pi*e/16
+        // F[m][r] = cos - i sin;  Yr = sum cos Xr + sin Xi;  Yi = sum -sin Xr + cos Xi
+        ar[i] = float(k < 16 ? cs : sn);
+        ai[i] = float(k < 16 ? -sn : cs);
+    }
+    typename MfmaOps<PREC>::V rh, rl, ih, il;
+    split_hilo<PREC>(ar, rh, rl);
+    split_hilo<PREC>(ai, ih, il);
+    out[4 * lane + 0] = rh;
+    out[4 * lane + 1] = rl;
+    out[4 * lane + 2] = ih;
+    out[4 * lane + 3] = il;
+}
 
 // The whole radix-16 stage schedule of a tile on the matrix cores.  N is a
 // power of 16 (every stage radix 16); each wave owns 64 butterflies per stage
@@ -529,10 +585,9 @@ __device__ __forceinline__ void mfma_stages(float2 *v, float2 *tile, int pitch, 
                 mx = fmaxf(mx, __shfl_xor(mx, 16));
                 mx = fmaxf(mx, __shfl_xor(mx, 32));
                 if (mx > 0.f) {
-                    int e;
-                    (void)frexpf(mx, &e); // mx in [2^(e-1), 2^e)
-                    scale = ldexpf(1.f, 15 - e);
-                    unscale = ldexpf(1.f, e - 15);
+                    const int e = __builtin_amdgcn_frexp_expf(mx); // mx in [2^(e-1), 2^e)
+                    scale = __builtin_amdgcn_ldexpf(1.f, 15 - e);
+                    unscale = __builtin_amdgcn_ldexpf(1.f, e - 15);
                 }
 #pragma unroll
                 for (int i = 0; i < 8; ++i) x[g][i] *= scale;

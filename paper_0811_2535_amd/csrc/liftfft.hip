@@ -83,6 +83,7 @@ struct PassArgs {
     int32_t pitch;  // exchange line pitch, in exchange elements
     const int64_t *offsets; // packed uneven batch: first element of each transform (else b*n)
     int64_t total;          // packed uneven batch: elements in the buffer
+    const void *dft_ops;    // matrix-core forms: the DFT-matrix operand table
     // Axis passes of a three-level lift (K_AXIS, K_AXIS_WIDE).  Line l of a transform is
     // (lm, ld) = (l mod 2^ax_log2U, l div 2^ax_log2U); element i of the line
     // sits at (lm << ax_in[0]) + (ld << ax_in[1]) + (i << ax_in[2]) and
@@ -140,7 +141,7 @@ constexpr int CP_LOAD1 = 0, CP_STORE1 = 0, CP_LOAD2 = 0, CP_STORE2 = 0;
 //   PREC   PREC_FP32: stages in FP32 on the vector units; PREC_F16X2 /
 //          PREC_BF16X2: radix-16 stages on the matrix cores (mfma_stages)
 struct NoOperands {
-    __device__ __forceinline__ explicit NoOperands(int) {}
+    __device__ __forceinline__ NoOperands(int, const void *) {}
 };
 template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PREC = PREC_FP32> struct Tile {
     using C = typename Cx<Real>::T;
@@ -166,7 +167,8 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
     C *__restrict__ out;
     int64_t pmask, qmask;
 
-    __device__ __forceinline__ Tile(const PassArgs &args, unsigned char *smem) : a(args), F(int(threadIdx.x & 63)) {
+    __device__ __forceinline__ Tile(const PassArgs &args, unsigned char *smem)
+        : a(args), F(int(threadIdx.x & 63), args.dft_ops) {
         log2T = a.log2T;
         T = 1 << log2T;
         tid = threadIdx.x;
@@ -223,6 +225,11 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
         return ((lm + c) << st[0]) + (ld << st[1]) + (int64_t(j) << st[2]);
     }
 
+    // Pass C of a three-level lift (contiguous rows, complex exchange, FP32
+    // stages, one first-stage butterfly per thread): loaded row first.
+    static constexpr bool ROWS_FIRST_KIND = KIND == K_AXIS && !SPLIT && PREC == PREC_FP32 && TILE && E == R0;
+    __device__ __forceinline__ bool rows_first() const { return ROWS_FIRST_KIND && a.ax_in[2] == 0; }
+
     // Data loads of the tile starting at line0: a buffer descriptor, one
     // 32-bit lane offset, and a uniform per-slot offset.  Raw values: the
     // conjugation of sign +1 is applied by the caller, so that a prefetch is
@@ -252,37 +259,22 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
             for (int s = 0; s < E; ++s) v[s] = src[int64_t(slot_off<N, E, R0>(s)) << a.ax_in[2]];
         } else if constexpr (KIND == K_AXIS) {
             const rsrc_t src = make_rsrc(in + base(line0 >> a.ax_log2L), uint32_t(a.n) * ES);
-            if constexpr (!SPLIT && PREC == PREC_FP32 && TILE) {
-                if (a.ax_in[2] == 0) {
-                    // Pass C's lines are contiguous rows: read them row first
-                    // (a wavefront instruction covers TPL consecutive elements
-                    // of each of 64/TPL lines instead of 64/T elements of each
-                    // of T lines) and hand the values to their line-first
-                    // owners through the LDS tile.  Every thread reaches both
-                    // barriers: axis tiles are whole (T divides the lines).
-                    const int cr = tid / TPL, jr = tid % TPL;
-                    const uint32_t l = uint32_t(line0 & ((int64_t(1) << a.ax_log2L) - 1));
-                    const uint32_t lm = l & ((1u << a.ax_log2U) - 1), ld = l >> a.ax_log2U;
-                    const uint32_t rlane = (((lm + uint32_t(cr)) << a.ax_in[0]) + (ld << a.ax_in[1]) + uint32_t(jr)) * ES;
-                    C t[E];
+            if (rows_first()) {
+                // Pass C's lines are contiguous rows: read them row first (a
+                // wavefront instruction covers TPL consecutive elements of
+                // each of 64/TPL lines instead of 64/T elements of each of T
+                // lines).  Thread (cr, jr) = (tid / TPL, tid % TPL) holds the
+                // inputs of the first stage's butterfly jr of line cr;
+                // transform_store runs that stage in this layout and hands
+                // the results to their line-first owners through the stage
+                // exchange.
+                const int cr = tid / TPL, jr = tid % TPL;
+                const uint32_t l = uint32_t(line0 & ((int64_t(1) << a.ax_log2L) - 1));
+                const uint32_t lm = l & ((1u << a.ax_log2U) - 1), ld = l >> a.ax_log2U;
+                const uint32_t rlane = (((lm + uint32_t(cr)) << a.ax_in[0]) + (ld << a.ax_in[1]) + uint32_t(jr)) * ES;
 #pragma unroll
-                    for (int s = 0; s < E; ++s) t[s] = buf_load(in, src, rlane, uint32_t(slot_off<N, E, R0>(s)) * ES);
-                    C *wl = tile + cr * a.pitch;
-#pragma unroll
-                    for (int s = 0; s < E; ++s) {
-                        const int e = jr + slot_off<N, E, R0>(s);
-                        wl[e + (e >> 4)] = t[s];
-                    }
-                    __syncthreads();
-                    const C *rl = tile + c * a.pitch;
-#pragma unroll
-                    for (int s = 0; s < E; ++s) {
-                        const int e = j + slot_off<N, E, R0>(s);
-                        v[s] = rl[e + (e >> 4)];
-                    }
-                    __syncthreads(); // the stage loop's first exchange writes the tile
-                    return;
-                }
+                for (int s = 0; s < E; ++s) v[s] = buf_load(in, src, rlane, uint32_t(slot_off<N, E, R0>(s)) * ES);
+                return;
             }
             const uint32_t lane = axis_lane(line0, a.ax_in);
 #pragma unroll
@@ -456,8 +448,36 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
         const bool active = line0 + c < a.lines;
         if constexpr ((KIND == K_PASS1 || AXIS) && !TILE) __syncthreads();
 
-        if constexpr (PREC == PREC_FP32) run_stages<C, N, RMAX, E, SPLIT>(v, line, twl, j);
-        else mfma_stages<PREC, N>(v, tile, a.pitch, twl, c, j, tid, F);
+        if constexpr (ROWS_FIRST_KIND) {
+            if (rows_first()) {
+                // First stage (no twiddles) on the row-first layout of load():
+                // butterfly jr of line cr writes output r to element 16 jr + r
+                // of its line, then every thread reads its line-first inputs
+                // of stage 1 and the stage loop continues from there.  Every
+                // thread reaches the barrier: axis tiles are whole.
+                const int cr = tid / TPL, jr = tid % TPL;
+                dft<R0>(v);
+                C *wl = tile + cr * a.pitch;
+#pragma unroll
+                for (int r = 0; r < R0; ++r) wl[lpad<N>(jr * R0 + r)] = v[r];
+                __syncthreads();
+                constexpr int R1 = sched_radix(N, RMAX, 1), NB1 = E / R1;
+                const C *ln = tile + c * a.pitch;
+#pragma unroll
+                for (int i = 0; i < NB1; ++i) {
+                    const int b = j + i * TPL;
+#pragma unroll
+                    for (int r = 0; r < R1; ++r) v[i * R1 + r] = ln[lpad<N>(b + r * (N / R1))];
+                }
+                run_stages<C, N, RMAX, E, SPLIT, 1>(v, line, twl, j);
+            } else {
+                run_stages<C, N, RMAX, E, SPLIT>(v, line, twl, j);
+            }
+        } else if constexpr (PREC == PREC_FP32) {
+            run_stages<C, N, RMAX, E, SPLIT>(v, line, twl, j);
+        } else {
+            mfma_stages<PREC, N>(v, tile, a.pitch, twl, c, j, tid, F);
+        }
 
         if (!active) return;
         if constexpr (KIND == K_SINGLE) {
@@ -645,6 +665,86 @@ __global__ __launch_bounds__((max_threads<Real, EMAX, PERSIST>()), (min_waves<DE
 }
 
 // ---------------------------------------------------------------------------
+// Axis pass of a three-level lift with 256-point lines (complex64) whose
+// stage exchange is done by wavefront shuffles instead of the LDS tile.  A
+// workgroup of 256 threads takes 16 adjacent lines; thread (c, j) = (tid >> 4,
+// tid & 15) holds elements j + 16 r (r < 16) of line c, so each line's 16
+// threads are one 16-lane DPP row.  Stage 0 is butterfly j's 16-point DFT;
+// element 16 j' + r of its output is input r' = j' of stage 1's butterfly r,
+// which a 16 x 16 transpose within the row (transpose16_row) delivers; stage
+// 1 (twiddles w_256^(-r j), 16-point DFT) leaves output k = j + 16 r in v[r].
+// LDS holds only the stage twiddles and the per-line weight factors.  The
+// same loads, weights and stores as the LDS-tile axis kernel, with lanes
+// sweeping a line's elements first instead of the lines first.
+constexpr int SHUF_N = 256, SHUF_T = 16, SHUF_THREADS = 256;
+
+__global__ __launch_bounds__(SHUF_THREADS) void axis_shuffle_kernel(PassArgs a) {
+    using C = float2;
+    constexpr uint32_t ES = sizeof(C);
+    __shared__ C twl[SHUF_N];         // w_256^e, e < 256 (+1 root)
+    __shared__ C ep[SHUF_T * 16];     // P[c][r] = w_n^(u(c) m 16 r)
+    const int64_t t = tile_of<false>(a, 0);
+    if (t < 0) return;
+    const int tid = threadIdx.x, c = tid >> 4, j = tid & 15;
+    const int64_t line0 = t * SHUF_T;
+    const int64_t b = line0 >> a.ax_log2L;
+    const uint32_t l = uint32_t(line0 & ((int64_t(1) << a.ax_log2L) - 1));
+    const uint32_t lm = l & ((1u << a.ax_log2U) - 1), ld = l >> a.ax_log2U;
+    const C *in = static_cast<const C *>(a.in) + b * a.n;
+    C *out = static_cast<C *>(a.out) + b * a.n;
+    const rsrc_t src = make_rsrc(in, uint32_t(a.n) * ES), dst = make_rsrc(out, uint32_t(a.n) * ES);
+    auto lane_off = [&](const int32_t *st) {
+        return (((lm + uint32_t(c)) << st[0]) + (ld << st[1]) + (uint32_t(j) << st[2])) * ES;
+    };
+    // Table entries first (loads complete in order), then the data.
+    const C *__restrict__ tw = static_cast<const C *>(a.tw);
+    const C tw_own = tw[tid];
+    const bool weighted = a.ax_tw != 0;
+    uint32_t u0 = 0, du = 0, k0 = 0;
+    if (a.ax_tw == 2) {
+        u0 = lm;
+        du = 1;
+        k0 = ld;
+    } else if (a.ax_tw == 1) {
+        u0 = ld << a.ax_log2U;
+    }
+    const uint32_t m = uint32_t(a.ax_log2m), nmask = uint32_t(a.n - 1), lomask = (1u << a.log2h) - 1;
+    const C *__restrict__ hi = static_cast<const C *>(a.tw_hi);
+    const C *__restrict__ lo = static_cast<const C *>(a.tw_lo);
+    // A = w_n^(u(c) (k0 + m j)) for this thread; P entry (cp, rp) = (tid >> 4, tid & 15).
+    const uint32_t xa = weighted ? ((u0 + du * uint32_t(c)) * (k0 + (uint32_t(j) << m))) & nmask : 0u;
+    const uint32_t xp = weighted ? ((u0 + du * uint32_t(c)) * (uint32_t(16 * j) << m)) & nmask : 0u;
+    const C ahi = hi[xa >> a.log2h], alo = lo[xa & lomask], phi = hi[xp >> a.log2h], plo = lo[xp & lomask];
+    C v[16];
+    const uint32_t li = lane_off(a.ax_in);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = buf_load(in, src, li, (uint32_t(16 * r) << a.ax_in[2]) * ES);
+    twl[tid] = tw_own;
+    ep[tid] = cmul(phi, plo); // entry (c, r = j)
+    const C A = cmul(ahi, alo);
+    const float sin_ = a.conj_in ? -1.f : 1.f, sout = a.conj_out ? -1.f : 1.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = scale_im(v[r], sin_);
+    dft16(v);
+    transpose16_row(v, j);
+    __syncthreads(); // twl and ep published
+#pragma unroll
+    for (int r = 1; r < 16; ++r) v[r] = cmulc(v[r], twl[r * j]);
+    dft16(v);
+    const uint32_t lo_off = lane_off(a.ax_out);
+    if (weighted) {
+        const C *P = ep + c * 16;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            buf_store(cmulc(v[r], cmul(A, P[r])), dst, lo_off, (uint32_t(16 * r) << a.ax_out[2]) * ES);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            buf_store(scale_im(v[r], sout), dst, lo_off, (uint32_t(16 * r) << a.ax_out[2]) * ES);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Packed batches of uneven power-of-two lengths.  The plan groups the
 // transforms into classes of equal length.  Lengths up to 2^12 run through
 // the single-pass kernel, one launch per class, with `a.offsets` listing
@@ -796,9 +896,11 @@ struct Variant {
     bool persist = false; // persistent workgroups with next-tile prefetch
     bool dense = false;   // 64-VGPR cap (two 1024-thread workgroups per CU)
     int prec = 0;         // PREC_*: radix-16 stages on the matrix cores when nonzero
-    bool is_default() const { return emax == 16 && !split && !persist && !dense && !prec; }
+    bool shuffle = false; // axis passes: stage exchange by wavefront shuffles
+    bool is_default() const { return emax == 16 && !split && !persist && !dense && !prec && !shuffle; }
     int code() const {
-        return (emax == 32 ? 1 : 0) | (split ? 2 : 0) | (persist ? 4 : 0) | (dense ? 8 : 0) | (prec << 4);
+        return (emax == 32 ? 1 : 0) | (split ? 2 : 0) | (persist ? 4 : 0) | (dense ? 8 : 0) | (prec << 4) |
+               (shuffle ? 64 : 0);
     }
 };
 
@@ -891,6 +993,10 @@ KernelFn pick_kernel(int dtype, int kind, int log2N, int rmax, const Variant &v)
                                     : pick_mfma_kind<PREC_BF16X2>(kind, log2N);
     }
     if (kind == K_AXIS_WIDE && !v.is_default()) return nullptr;
+    if (v.shuffle) { // complex64 axis passes over 256-point lines
+        if (kind != K_AXIS || dtype != FFT_C64 || rmax != 16 || log2N != 8 || v.code() != 64) return nullptr;
+        return &axis_shuffle_kernel;
+    }
     if (kind == K_AXIS && !v.is_default()) { // the split exchange (complex64) only
         if (dtype != FFT_C64 || rmax != 16 || v.code() != 2) return nullptr;
         return pick<float, K_AXIS, 16, 2, AXIS_LMIN, AXIS_LMAX>(log2N);
@@ -946,6 +1052,8 @@ struct fft_plan {
     int log2W = 0;        // scratch slab width (two-pass plans)
     bool no_remap = false;
     int precision = 0;
+    void *dft_ops = nullptr; // matrix-core forms: DFT-matrix operand table (4 KB per form)
+    int dft_ops_prec = 0;    // the form whose operands dft_ops holds
     int64_t total = 0; // elements in the input (and output) buffer
     // Packed batch of uneven lengths: two persistent launches over classes
     // of equal length, replayed as one captured graph per (in, out, sign).
@@ -1055,6 +1163,10 @@ bool fill_launch(Launch &L, int dtype, int kind, int log2N, int rmax, int log2T,
     if (ts.lds > LDS_BUDGET) return false;
     L.pitch = ts.pitch;
     L.lds = size_t(ts.lds);
+    if (v.shuffle) { // fixed shape: 16 lines of 256 points, tables in static LDS
+        if ((int64_t(1) << log2T) != SHUF_T || L.threads != SHUF_THREADS) return false;
+        L.lds = 0;
+    }
     if (L.lds > 65536 &&
         hipFuncSetAttribute(reinterpret_cast<const void *>(L.fn),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(L.lds)) != hipSuccess) {
@@ -1180,6 +1292,7 @@ void free_plan(fft_plan *p) {
     if (p->scratch) (void)hipFree(p->scratch);
     if (p->tables) (void)hipFree(p->tables);
     if (p->meta) (void)hipFree(p->meta);
+    if (p->dft_ops) (void)hipFree(p->dft_ops);
     delete p;
 }
 
@@ -1344,7 +1457,13 @@ int shape_plan(fft_plan *p, int64_t n, int64_t batch, int dtype, const fft_plan_
     if (o.lines_per_block2 < 0 || (o.lines_per_block2 & (o.lines_per_block2 - 1))) return FFT_E_ARG;
     constexpr int32_t known_flags = FFT_OPT_NO_XCD_REMAP | FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE |
                                     FFT_OPT_PERSISTENT | FFT_OPT_ONE_TILE | FFT_OPT_DENSE |
-                                    FFT_OPT_TWO_LEVEL | FFT_OPT_THREE_LEVEL;
+                                    FFT_OPT_TWO_LEVEL | FFT_OPT_THREE_LEVEL | FFT_OPT_SHUFFLE_EXCHANGE;
+    // the shuffle exchange exists for three-level plans only, as the only variant
+    if ((o.flags & FFT_OPT_SHUFFLE_EXCHANGE) &&
+        (!(o.flags & FFT_OPT_THREE_LEVEL) || (o.flags & (FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE |
+                                                           FFT_OPT_PERSISTENT | FFT_OPT_DENSE)) ||
+         o.values_per_thread))
+        return FFT_E_ARG;
     if (o.flags & ~known_flags) return FFT_E_ARG;
     if ((o.flags & FFT_OPT_TWO_LEVEL) && (o.flags & FFT_OPT_THREE_LEVEL)) return FFT_E_ARG;
     if ((o.flags & FFT_OPT_THREE_LEVEL) && (o.log2_p || o.lines_per_block2 || o.values_per_thread2 ||
@@ -1363,6 +1482,7 @@ int shape_plan(fft_plan *p, int64_t n, int64_t batch, int dtype, const fft_plan_
     if (o.flags & FFT_OPT_SPLIT_EXCHANGE) var.split = true;
     if (o.flags & FFT_OPT_PERSISTENT) var.persist = true;
     if (o.flags & FFT_OPT_DENSE) var.dense = true;
+    if (o.flags & FFT_OPT_SHUFFLE_EXCHANGE) var.shuffle = true;
     Variant var2 = var;
     if (o.values_per_thread2) var2.emax = o.values_per_thread2;
     const bool forced = !var.is_default() || !var2.is_default();
@@ -1395,11 +1515,20 @@ int shape_plan(fft_plan *p, int64_t n, int64_t batch, int dtype, const fft_plan_
         }
         const int want = o.lines_per_block;
         const int kind = n * int64_t(esize) > (int64_t(1) << 31) ? K_AXIS_WIDE : K_AXIS;
-        if (!plan_pass(p->k1, dtype, kind, l3, radix, int64_t(1) << l1, batch << (l1 + l2), want, 0, var,
+        // The shuffle exchange applies to the passes over 256-point lines;
+        // the others keep the default kernel.
+        auto axis_var = [&](int l2N) {
+            Variant v = var;
+            if (v.shuffle && (l2N != 8 || dtype != FFT_C64 || kind != K_AXIS)) v.shuffle = false;
+            return v;
+        };
+        if (var.shuffle && ((l1 != 8 && l2 != 8 && l3 != 8) || dtype != FFT_C64 || kind != K_AXIS))
+            return FFT_E_UNSUPPORTED;
+        if (!plan_pass(p->k1, dtype, kind, l3, radix, int64_t(1) << l1, batch << (l1 + l2), want, 0, axis_var(l3),
                        p->device) ||
-            !plan_pass(p->k2, dtype, kind, l2, radix, int64_t(1) << l1, batch << (l1 + l3), want, 0, var,
+            !plan_pass(p->k2, dtype, kind, l2, radix, int64_t(1) << l1, batch << (l1 + l3), want, 0, axis_var(l2),
                        p->device) ||
-            !plan_pass(p->k3, dtype, kind, l1, radix, int64_t(1) << l3, batch << (l2 + l3), want, 0, var,
+            !plan_pass(p->k3, dtype, kind, l1, radix, int64_t(1) << l3, batch << (l2 + l3), want, 0, axis_var(l1),
                        p->device)) {
             return FFT_E_UNSUPPORTED;
         }
@@ -1887,6 +2016,7 @@ int launch_plan(const fft_plan *p, const void *in, void *out, int sign, hipStrea
     a.log2p = p->log2p;
     a.log2q = p->log2q;
     a.log2h = p->log2h;
+    a.dft_ops = p->dft_ops;
     int rc = FFT_OK;
     const hipEvent_t *ev = nullptr;
     if (p->timing) {
@@ -2144,6 +2274,27 @@ int fft_plan_set_precision(fft_plan *p, int mode) {
     };
     if (!redo(n1, p->base1) || (p->passes >= 2 && !redo(n2, p->base2)) || (p->passes == 3 && !redo(n3, p->base3)))
         return FFT_E_UNSUPPORTED;
+    if (mode != FFT_PREC_FP32 && p->dft_ops_prec != mode) {
+        // The 16 x 16 DFT matrix in this form's operand layout, hi and lo
+        // parts, generated once from FP64 angles.
+        constexpr size_t OPS_BYTES = 64 * 4 * 16;
+        if (!p->dft_ops && hipMalloc(&p->dft_ops, OPS_BYTES) != hipSuccess) {
+            (void)hipGetLastError();
+            p->dft_ops = nullptr;
+            return FFT_E_OOM;
+        }
+        if (mode == FFT_PREC_F16X2)
+            hipLaunchKernelGGL(dft_operand_table<PREC_F16X2>, dim3(1), dim3(64), 0, 0,
+                               static_cast<MfmaOps<PREC_F16X2>::V *>(p->dft_ops));
+        else
+            hipLaunchKernelGGL(dft_operand_table<PREC_BF16X2>, dim3(1), dim3(64), 0, 0,
+                               static_cast<MfmaOps<PREC_BF16X2>::V *>(p->dft_ops));
+        if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+            p->dft_ops_prec = 0;
+            return FFT_E_HIP;
+        }
+        p->dft_ops_prec = mode;
+    }
     p->k1 = n1;
     p->k2 = n2;
     p->k3 = n3;
@@ -2251,18 +2402,29 @@ std::vector<fft_plan_opts> tune_candidates(int t, int dtype) {
     return c;
 }
 
+// Buffer sets the tuner rotates between executes, so that no candidate reads
+// an input still resident in the 256 MB last-level cache from its previous
+// execute (as a workload over distinct buffers would not); one set once a
+// buffer is at least 512 MB, which the cache cannot hold anyway.
+constexpr int TUNE_SETS = 3;
+constexpr size_t TUNE_ROTATE_BELOW = size_t(512) << 20;
+
 struct TuneBench {
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    void *x = nullptr, *y = nullptr, *ref = nullptr;
+    void *x[TUNE_SETS] = {}, *y[TUNE_SETS] = {}, *ref = nullptr;
+    int sets = 1;
+    int last = 0; // set whose output the last execute wrote
     double *partial = nullptr;
     int64_t count = 0;
     int dtype = 0;
     ~TuneBench() {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
-        if (x) (void)hipFree(x);
-        if (y) (void)hipFree(y);
+        for (int k = 0; k < TUNE_SETS; ++k) {
+            if (x[k]) (void)hipFree(x[k]);
+            if (y[k]) (void)hipFree(y[k]);
+        }
         if (ref) (void)hipFree(ref);
         if (partial) (void)hipFree(partial);
         if (st) (void)hipStreamDestroy(st);
@@ -2270,11 +2432,19 @@ struct TuneBench {
 };
 constexpr int CMP_BLOCKS = 1024;
 
-// Milliseconds per forward execute of `plan` (negative on failure).
+// Milliseconds per forward execute of `plan` (negative on failure), each
+// execute on the next buffer set.
 double tune_time(const fft_plan *plan, TuneBench &b) {
-    for (int w = 0; w < 2; ++w)
-        if (fft_execute(plan, b.x, b.y, -1, b.st) != FFT_OK) return -1;
-    if (hipEventRecord(b.e0, b.st) != hipSuccess || fft_execute(plan, b.x, b.y, -1, b.st) != FFT_OK ||
+    int k = 0;
+    auto exec = [&]() {
+        b.last = k;
+        const int rc = fft_execute(plan, b.x[k], b.y[k], -1, b.st);
+        k = (k + 1) % b.sets;
+        return rc;
+    };
+    for (int w = 0; w < 2 * b.sets; ++w)
+        if (exec() != FFT_OK) return -1;
+    if (hipEventRecord(b.e0, b.st) != hipSuccess || exec() != FFT_OK ||
         hipEventRecord(b.e1, b.st) != hipSuccess || hipEventSynchronize(b.e1) != hipSuccess)
         return -1;
     float one = 0;
@@ -2283,7 +2453,7 @@ double tune_time(const fft_plan *plan, TuneBench &b) {
     reps = reps < 3 ? 3 : reps > 50 ? 50 : reps;
     if (hipEventRecord(b.e0, b.st) != hipSuccess) return -1;
     for (int r = 0; r < reps; ++r)
-        if (fft_execute(plan, b.x, b.y, -1, b.st) != FFT_OK) return -1;
+        if (exec() != FFT_OK) return -1;
     float ms = 0;
     if (hipEventRecord(b.e1, b.st) != hipSuccess || hipEventSynchronize(b.e1) != hipSuccess ||
         hipEventElapsedTime(&ms, b.e0, b.e1) != hipSuccess)
@@ -2292,14 +2462,15 @@ double tune_time(const fft_plan *plan, TuneBench &b) {
 }
 
 // Largest |y - ref| relative to the largest |ref| (after tune_time left the
-// candidate's output in y).
+// candidate's output in y[last]; every input set holds the same pattern).
 double tune_diff(TuneBench &b) {
+    const void *y = b.y[b.last];
     if (b.dtype == FFT_C64)
         hipLaunchKernelGGL(compare_kernel<float>, dim3(CMP_BLOCKS), dim3(CMP_THREADS), 0, b.st,
-                           static_cast<const float2 *>(b.y), static_cast<const float2 *>(b.ref), b.count, b.partial);
+                           static_cast<const float2 *>(y), static_cast<const float2 *>(b.ref), b.count, b.partial);
     else
         hipLaunchKernelGGL(compare_kernel<double>, dim3(CMP_BLOCKS), dim3(CMP_THREADS), 0, b.st,
-                           static_cast<const double2 *>(b.y), static_cast<const double2 *>(b.ref), b.count,
+                           static_cast<const double2 *>(y), static_cast<const double2 *>(b.ref), b.count,
                            b.partial);
     std::vector<double> h(2 * CMP_BLOCKS);
     if (hipGetLastError() != hipSuccess ||
@@ -2353,20 +2524,26 @@ int fft_plan_create_tuned(int64_t n, int64_t batch, int dtype, int32_t max_candi
         fft_plan_destroy(best);
         return FFT_E_HIP;
     }
-    if (hipMalloc(&b.x, bytes) != hipSuccess || hipMalloc(&b.y, bytes) != hipSuccess ||
-        hipMalloc(&b.ref, bytes) != hipSuccess || hipMalloc(&b.partial, 2 * CMP_BLOCKS * sizeof(double)) != hipSuccess) {
+    b.sets = bytes < TUNE_ROTATE_BELOW ? TUNE_SETS : 1;
+    bool ok = hipMalloc(&b.ref, bytes) == hipSuccess &&
+              hipMalloc(&b.partial, 2 * CMP_BLOCKS * sizeof(double)) == hipSuccess;
+    for (int k = 0; ok && k < b.sets; ++k)
+        ok = hipMalloc(&b.x[k], bytes) == hipSuccess && hipMalloc(&b.y[k], bytes) == hipSuccess;
+    if (!ok) {
         (void)hipGetLastError();
         fft_plan_destroy(best);
         return FFT_E_OOM;
     }
     const int64_t fb = (b.count + 255) / 256;
-    if (dtype == FFT_C64)
-        hipLaunchKernelGGL(fill_pattern_kernel<float>, dim3(unsigned(fb)), dim3(256), 0, b.st,
-                           static_cast<float2 *>(b.x), b.count);
-    else
-        hipLaunchKernelGGL(fill_pattern_kernel<double>, dim3(unsigned(fb)), dim3(256), 0, b.st,
-                           static_cast<double2 *>(b.x), b.count);
-    if (hipGetLastError() != hipSuccess || fft_execute(best, b.x, b.ref, -1, b.st) != FFT_OK ||
+    for (int k = 0; k < b.sets; ++k) {
+        if (dtype == FFT_C64)
+            hipLaunchKernelGGL(fill_pattern_kernel<float>, dim3(unsigned(fb)), dim3(256), 0, b.st,
+                               static_cast<float2 *>(b.x[k]), b.count);
+        else
+            hipLaunchKernelGGL(fill_pattern_kernel<double>, dim3(unsigned(fb)), dim3(256), 0, b.st,
+                               static_cast<double2 *>(b.x[k]), b.count);
+    }
+    if (hipGetLastError() != hipSuccess || fft_execute(best, b.x[0], b.ref, -1, b.st) != FFT_OK ||
         hipStreamSynchronize(b.st) != hipSuccess) {
         (void)hipGetLastError();
         fft_plan_destroy(best);

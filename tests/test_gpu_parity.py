@@ -295,3 +295,18 @@ def test_scratch_slab_widths(lf, t, batch):
                        lines_per_block2=T2, flags=2)
         errs = [oracle.rel_l2(got[b], ref[b]) for b in range(batch)]
         assert max(errs) <= TOL[np.complex64], (W, vpt2, T1, T2, errs)
+
+
+def test_complex128_repeat_determinism(lf, torch):
+    """complex128 results are bitwise identical across repeated executes, on
+    single-pass, two-level and three-level plans (every element store of a
+    complex128 value is issued as two 8-byte stores), and each repeat meets
+    the oracle tolerance: 256 + 32 + 4 transforms per shape."""
+    for t, batch, reps, flags in ((12, 64, 4, 0), (18, 4, 8, 128), (24, 1, 4, 256)):
+        n = 1 << t
+        x_np = datagen.signals(n, batch, np.complex128, "normal", 120 + t)
+        announce("c128 repeat determinism n=2^%d batch=%d reps=%d" % (t, batch, reps))
+        outs = run_plan(lf, x_np, 1, repeat=reps, flags=flags)
+        for k in range(1, reps):
+            assert np.array_equal(outs[k].view(np.uint64), outs[0].view(np.uint64)), (t, k)
+        check_rows(outs[0], x_np, 1, TOL[np.complex128])

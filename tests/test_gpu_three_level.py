@@ -256,3 +256,36 @@ def test_default_lift_by_size(lf, torch):
         p.destroy()
         assert info["levels"] == info["passes"] == levels, (t, dt, opts, info["levels"])
 
+
+
+SHUFFLE = 512  # FFT_OPT_SHUFFLE_EXCHANGE
+
+
+@pytest.mark.parametrize("t,batch", [(24, 1), (23, 1), (22, 2), (25, 1)])
+def test_shuffle_exchange(lf, torch, t, batch):
+    """Axis passes over 256-point lines with the stage exchange done by
+    wavefront shuffles (DPP and ds_swizzle within 16-lane rows); passes over
+    other lengths keep the LDS-tile kernel.  Both signs, against the oracle,
+    and in place."""
+    n = 1 << t
+    x_np = datagen.signals(n, batch, np.complex64, "normal", 90 + t)
+    l1, l2, l3 = factors(t)
+    for sign in (-1, 1):
+        announce("three-level shuffle exchange t=%d batch=%d sign=%d" % (t, batch, sign))
+        got, info = run3(lf, x_np, sign, flags=THREE | SHUFFLE)
+        shuffled = [bool(info[k] & 64) for k in ("variant_pass1", "variant_pass2")]
+        assert shuffled == [l3 == 8, l2 == 8], (t, info)
+        check(got, x_np, sign, 1e-6, "shuffle t=%d" % t)
+    got, _ = run3(lf, x_np, -1, flags=THREE | SHUFFLE, in_place=True)
+    check(got, x_np, -1, 1e-6, "shuffle in place t=%d" % t)
+
+
+def test_shuffle_exchange_refusals(lf, torch):
+    from paper_0811_2535_amd.binding import FFTError
+    for n, dt, flags, want in ((1 << 24, torch.complex128, THREE | SHUFFLE, "FFT_E_UNSUPPORTED"),
+                               (1 << 18, torch.complex64, THREE | SHUFFLE, "FFT_E_UNSUPPORTED"),
+                               (1 << 24, torch.complex64, SHUFFLE, "FFT_E_ARG"),
+                               (1 << 24, torch.complex64, THREE | SHUFFLE | 2, "FFT_E_ARG")):
+        with pytest.raises(FFTError) as ei:
+            lf.Plan(n, 1, dt, flags=flags)
+        assert ei.value.name == want, (n, dt, flags)
