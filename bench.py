@@ -130,6 +130,52 @@ def summarize_counters(fetch_csv: str, write_csv: str, log2n: int, out_path: str
     return rec
 
 
+def kernel_label(name: str) -> str:
+    """Short description of a kernel in a rocprofv3 trace of this benchmark."""
+    import re
+    m = re.search(r"pass_kernel<(float|double), (\d+), (\d+), (\d), (\d+), (\w+), (\w+), (\w+), (\d)>", name)
+    if m:
+        real, N, rmax, kind, emax, split, persist, dense, prec = m.groups()
+        kinds = {"0": "single pass", "1": "pass 1", "2": "pass 2", "3": "axis pass", "4": "axis pass (64-bit)"}
+        parts = ["%s, %s-point lines" % (kinds[kind], N), "c64" if real == "float" else "c128"]
+        if rmax != "16":
+            parts.append("radix %s" % rmax)
+        if emax != "16":
+            parts.append("%s values/thread" % emax)
+        if split == "true":
+            parts.append("split exchange")
+        if persist == "true":
+            parts.append("persistent")
+        if dense == "true":
+            parts.append("64-VGPR cap")
+        if prec != "0":
+            parts.append({"1": "FP16 pairs on MFMA", "2": "BF16 pairs on MFMA"}[prec])
+        return ", ".join(parts)
+    for key, label in (("axis_shuffle_kernel", "axis pass, 256-point lines, shuffle exchange"),
+                       ("ragged_kernel", "uneven batch, persistent lifted passes"),
+                       ("block_phase", "paper's plan, block phase"), ("cyclic_phase", "paper's plan, cyclic phase"),
+                       ("twiddle_table_kernel", "FP64 weight tables"), ("dft_operand_table", "MFMA operand table"),
+                       ("neg_kernel", "streaming reference (torch.neg)"), ("copyBuffer", "host/device copies"),
+                       ("fill_pattern", "tuner input"), ("compare_kernel", "tuner check")):
+        if key in name:
+            return label
+    return name[:60]
+
+
+def summarize_trace(stats_csv: str) -> str:
+    """Markdown table of a rocprofv3 --stats kernel summary of this benchmark:
+    calls, average and min/max duration per kernel, largest total first."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["| kernel | calls | avg us | min us | max us | total % |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        out.append("| %s | %s | %.1f | %.1f | %.1f | %.2f |" % (
+            kernel_label(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    return "\n".join(out)
+
+
 def host_facts() -> dict:
     """CPU model and core counts of the host the oracle legs run on."""
     model = "unknown"
@@ -371,8 +417,14 @@ def measure_ragged(torch, lf, datagen, reps: int = 10) -> dict:
     ys = [torch.empty_like(xs[0]) for _ in range(sets)]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ms_mode = {}
-    for graph in (False, True):
-        plan = lf.Plan.uneven(lengths, torch.complex64, graph=graph)
+    # class plans on forked streams (the default), the persistent-launch
+    # form, each launched directly and replayed as a captured graph, and the
+    # class form with every class autotuned
+    for key, kw in ((("classes", False), {}), (("classes", True), {"graph": True}),
+                    (("persistent", False), {"persistent": True}),
+                    (("persistent", True), {"persistent": True, "graph": True}),
+                    (("tuned", False), {"autotune": True})):
+        plan = lf.Plan.uneven(lengths, torch.complex64, **kw)
         for i in range(sets):
             plan.execute(xs[i], ys[i], -1)
         torch.cuda.synchronize()
@@ -381,10 +433,11 @@ def measure_ragged(torch, lf, datagen, reps: int = 10) -> dict:
             plan.execute(xs[i % sets], ys[i % sets], -1)
         e1.record()
         torch.cuda.synchronize()
-        ms_mode[graph] = e0.elapsed_time(e1) / reps
-        info = plan.info()
+        ms_mode[key] = e0.elapsed_time(e1) / reps
+        if key == ("classes", False):
+            info = plan.info()
         plan.destroy()
-    ms_direct, ms_graph = ms_mode[False], ms_mode[True]
+    ms_direct, ms_graph = ms_mode[("classes", False)], ms_mode[("classes", True)]
     plan = lf.Plan.uneven(lengths, torch.complex64)
     plan.execute(xs[0], ys[0], -1)
     torch.cuda.synchronize()
@@ -431,15 +484,17 @@ def measure_ragged(torch, lf, datagen, reps: int = 10) -> dict:
     flops = sum(5.0 * ln * math.log2(ln) for ln in lengths)
     alg_bytes = sum((16 if ln <= 16384 else 32) * ln for ln in lengths)  # one pass up to 2^14
     return {"workload": "4096 c64 transforms, n = 2^k with k ~ U{8..16} (seed 3), packed, forward",
-            "elements": total, "length_classes": info["length_classes"],
+            "elements": total, "length_classes": info["length_classes"], "streams": info["streams"],
             "ms": round(ms_direct, 4), "ms_graph_replay": round(ms_graph, 4),
+            "ms_persistent_form": round(ms_mode[("persistent", False)], 4),
+            "ms_persistent_form_graph_replay": round(ms_mode[("persistent", True)], 4),
+            "ms_autotuned_classes": round(ms_mode[("tuned", False)], 4),
             "gflops": round(flops / (ms_direct * 1e-3) / 1e9, 1),
             "hbm_gbps_algorithmic": round(alg_bytes / (ms_direct * 1e-3) / 1e9, 1),
             "ms_per_class_batched_plans": round(ms_classes, 4),
             "ms_one_launch_per_transform": round(ms_each, 4),
             "speedup_vs_per_class": round(ms_classes / ms_direct, 3),
-            "speedup_vs_per_transform": round(ms_each / ms_direct, 3),
-            "grid": [info["grid_pass1"], info["grid_pass2"]]}, keep
+            "speedup_vs_per_transform": round(ms_each / ms_direct, 3)}, keep
 
 
 def measure_precision(torch, lf, datagen, reps: int = 5):
@@ -668,6 +723,46 @@ def run_sweep(torch, lf, log2n: int, sets: int = 4, reps: int = 12) -> int:
         plan_times("two-level %s" % fn, flags=TWO | flags)
     for lp in (10, 11, 13, 14):
         plan_times("two-level split p = 2^%d" % lp, flags=TWO, log2_p=lp)
+    plan_times("two-level, hardware workgroup order", flags=TWO | B.FFT_OPT_NO_XCD_REMAP)
+    plan_times("three-level, hardware workgroup order", flags=THREE | B.FFT_OPT_NO_XCD_REMAP)
+    return 0
+
+
+def run_lift_sweep(torch, lf, sizes, sets: int = 4, reps: int = 10) -> int:
+    """Two-level against three-level lift per length (c64, one transform,
+    rotating buffer sets, per-pass HIP events): where the library's default
+    switches lifts.  One JSON object per line."""
+    from paper_0811_2535_amd import binding as B
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream(dev)
+    for t in sizes:
+        n = 1 << t
+        nsets = sets if t <= 26 else 2
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(2)
+        xs = [torch.randn(n, dtype=torch.complex64, device=dev, generator=gen) for _ in range(nsets)]
+        ys = [torch.empty_like(x) for x in xs]
+        rec = {"log2n": t}
+        for flags, name in ((B.FFT_OPT_TWO_LEVEL, "two_level_us"), (B.FFT_OPT_THREE_LEVEL, "three_level_us")):
+            try:
+                p = lf.Plan(n, 1, torch.complex64, flags=flags)
+            except B.FFTError as ex:
+                rec[name] = ex.name
+                continue
+            for i in range(2):
+                p.execute(xs[i % nsets], ys[i % nsets], -1, st)
+            torch.cuda.synchronize()
+            p.set_timing(True)
+            p.read_timing(reset=True)
+            for i in range(reps):
+                p.execute(xs[i % nsets], ys[i % nsets], -1 if i % 2 == 0 else 1, st)
+            ms, cnt = p.read_timing(reset=True)
+            p.set_timing(False)
+            p.destroy()
+            rec[name] = [round(ms[k] / cnt[k] * 1e3, 1) for k in range(3) if cnt[k]]
+        print(json.dumps(rec), flush=True)
+        del xs, ys
+        torch.cuda.empty_cache()
     return 0
 
 
@@ -685,14 +780,24 @@ def main() -> int:
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary from two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of this benchmark and exit")
+    ap.add_argument("--summarize-trace", metavar="KERNEL_STATS_CSV",
+                    help="print a markdown table of a rocprofv3 --kernel-trace --stats summary of this "
+                         "benchmark (run_kernel_stats.csv) and exit")
     ap.add_argument("--sweep", action="store_true",
                     help="print per-pass kernel times of the plan configurations (tile widths, "
                          "kernel variants, lifts) with streaming references, one JSON object per "
                          "line, and exit")
+    ap.add_argument("--sweep-lifts", metavar="LOG2N,...",
+                    help="print two-level against three-level per-pass times at the given lengths "
+                         "(e.g. 20,22,23,24,25,26,28) and exit")
     ap.add_argument("--copy-reps", type=int, default=10,
                     help="device-to-device copies of one pass's bytes, timed for context and "
                          "used as the known-size reference kernel for HBM counters")
     args = ap.parse_args()
+
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace))
+        return 0
 
     if args.summarize_counters:
         rec = summarize_counters(args.summarize_counters[0], args.summarize_counters[1], args.log2n,
@@ -721,6 +826,8 @@ def main() -> int:
     torch.cuda.set_device(dev)
     if args.sweep:
         return run_sweep(torch, lf, args.log2n)
+    if args.sweep_lifts:
+        return run_lift_sweep(torch, lf, [int(v) for v in args.sweep_lifts.split(",")])
     n = 1 << args.log2n
     S = max(2, args.sets)
 

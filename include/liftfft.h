@@ -216,24 +216,36 @@ int fft_plan_create_ex(int64_t n, int64_t batch, int dtype, const fft_plan_opts 
  * buffer: transform i (length lengths[i] = 2^t_i, 1 <= t_i <= 24) occupies
  * elements [off_i, off_i + lengths[i]) with off_i the sum of the earlier
  * lengths.  The lengths are the run-time blocking parameters of one batch:
- * the plan groups equal lengths into classes.  Lengths up to one workgroup's
- * line (2^14 complex64, 2^13 complex128) run in one pass, one launch per
- * class; the longer ones share two persistent launches (pass 1 of every
- * lifted class, then pass 2; Sections 4.2-4.8 of the paper for the lift),
- * each walking a work list of tiles ordered by class, longest lines first.
- * fft_execute launches them directly on the execute stream.  With
- * flags = FFT_OPT_GRAPH it instead replays them as one captured graph per
- * (in, out, sign) triple (captured on a private stream the first time; up to
- * 16 per plan; then, or when the execute stream is itself being captured,
- * the kernels are launched directly).  Replays measure a few percent slower
- * than direct launches on MI355X, hence the default.  flags is 0 or
- * FFT_OPT_GRAPH; any other bit returns FFT_E_ARG.
+ * the plan groups equal lengths into classes (Sections 4.2-4.8 of the paper
+ * for the lift of the long ones).
+ * Default form: each class is planned like fft_plan_create(2^t, count) --
+ * one pass up to one workgroup's line (2^14 complex64, 2^13 complex128),
+ * else the two- or three-level lift -- and reads its transforms through a
+ * device list of their offsets; the classes run on up to four streams (the
+ * execute stream and three streams the plan creates), forked from and
+ * joined back into the execute stream, the largest classes first.
+ * flags (0 or an OR of):
+ *   FFT_OPT_AUTOTUNE    shape every class like fft_plan_create_tuned(2^t,
+ *                       count, dtype, 16) does (timed at plan creation,
+ *                       remembered per shape for the process)
+ *   FFT_OPT_GRAPH       replay the work as one captured graph per (in, out,
+ *                       sign) triple (captured on a private stream the first
+ *                       time, with the classes' streams as parallel branches;
+ *                       up to 16 per plan; then, or when the execute stream
+ *                       is itself being captured, the kernels are launched
+ *                       directly)
+ *   FFT_OPT_PERSISTENT  the persistent form instead: the lifted classes share
+ *                       two persistent launches (pass 1 of every lifted
+ *                       class, then pass 2), each walking a work list of
+ *                       tiles ordered by class, longest lines first; the
+ *                       single-pass classes get one launch each, all on the
+ *                       execute stream (not with FFT_OPT_AUTOTUNE)
+ * Any other bit, or AUTOTUNE with PERSISTENT, returns FFT_E_ARG.
  * Errors: FFT_E_NULL (lengths or plan_out NULL), FFT_E_SIZE (count < 1, a
- * length not a power of two >= 2), FFT_E_ARG (unknown flags),
- * FFT_E_UNSUPPORTED (a length above the maximum, or a packed buffer of 2^32
- * bytes or more).
+ * length not a power of two >= 2), FFT_E_ARG (flags), FFT_E_UNSUPPORTED (a
+ * length above the maximum, or a packed buffer of 2^32 bytes or more).
  */
-enum { FFT_OPT_GRAPH = 64 };
+enum { FFT_OPT_GRAPH = 64, FFT_OPT_AUTOTUNE = 1024 };
 int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, uint32_t flags,
                          fft_plan **plan_out);
 
@@ -329,6 +341,9 @@ typedef struct fft_plan_info {
     int32_t levels, log2_n1, log2_n2, log2_n3;
     int32_t lines_per_block_pass3, grid_pass3, threads_pass3, paper_breakpoint;
     int64_t lds_bytes_pass3;
+    /* streams: uneven batches in the default form, the streams their classes
+     * run on (1..4); 0 otherwise. */
+    int32_t streams, reserved2;
 } fft_plan_info;
 
 int fft_plan_get_info(const fft_plan *plan, fft_plan_info *info);

@@ -54,6 +54,7 @@ FFT_OPT_GRAPH = 64
 FFT_OPT_TWO_LEVEL = 128
 FFT_OPT_THREE_LEVEL = 256
 FFT_OPT_SHUFFLE_EXCHANGE = 512
+FFT_OPT_AUTOTUNE = 1024
 
 
 class PlanOpts(ctypes.Structure):
@@ -94,7 +95,8 @@ class PlanInfo(ctypes.Structure):
                 ("log2_n2", ctypes.c_int32), ("log2_n3", ctypes.c_int32),
                 ("lines_per_block_pass3", ctypes.c_int32), ("grid_pass3", ctypes.c_int32),
                 ("threads_pass3", ctypes.c_int32), ("paper_breakpoint", ctypes.c_int32),
-                ("lds_bytes_pass3", ctypes.c_int64)]
+                ("lds_bytes_pass3", ctypes.c_int64),
+                ("streams", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -201,17 +203,20 @@ class Plan:
         return self
 
     @classmethod
-    def uneven(cls, lengths, dtype=torch.complex64, graph: bool = False) -> "Plan":
+    def uneven(cls, lengths, dtype=torch.complex64, graph: bool = False, persistent: bool = False,
+               autotune: bool = False) -> "Plan":
         """A plan for transforms of the given power-of-two lengths packed back
         to back in one buffer (fft_plan_create_many); ``self.offsets`` holds
-        each transform's first element."""
+        each transform's first element.  ``persistent`` selects the
+        persistent-launch form, ``autotune`` tunes every length class."""
         self = cls.__new__(cls)
         self._h = ctypes.c_void_p()
         lens = [int(v) for v in lengths]
         arr = (ctypes.c_int64 * max(1, len(lens)))(*lens)
         self.dtype_code = dtype_code(dtype)
         self.torch_dtype = torch.complex64 if self.dtype_code == FFT_C64 else torch.complex128
-        flags = FFT_OPT_GRAPH if graph else 0
+        flags = (FFT_OPT_GRAPH if graph else 0) | (FFT_OPT_PERSISTENT if persistent else 0) | \
+            (FFT_OPT_AUTOTUNE if autotune else 0)
         rc = lib().fft_plan_create_many(arr, len(lens), self.dtype_code, flags, ctypes.byref(self._h))
         _check(rc, "fft_plan_create_many(count=%d)" % len(lens))
         self.lengths = lens

@@ -431,13 +431,16 @@ template <int D> __device__ __forceinline__ float xor_lanes(float x) {
 template <int D, typename C> __device__ __forceinline__ void transpose_step(C *v, int j) {
     const bool hi = (j & D) != 0;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        if (r & D) continue;
-        const int s = r | D;
-        const C send = hi ? v[r] : v[s];
-        const C recv = mk<C>(xor_lanes<D>(send.x), xor_lanes<D>(send.y));
-        if (hi) v[r] = recv;
-        else v[s] = recv;
+    for (int q = 0; q < 8; ++q) {
+        // the q-th register index with bit D clear, and its partner
+        const int r = ((q & ~(D - 1)) << 1) | (q & (D - 1)), s = r | D;
+        const C a = v[r], b = v[s];
+        // selects on values (not on which register to write), so that the
+        // array stays in registers
+        const float sx = hi ? a.x : b.x, sy = hi ? a.y : b.y;
+        const float rx = xor_lanes<D>(sx), ry = xor_lanes<D>(sy);
+        v[r] = mk<C>(hi ? rx : a.x, hi ? ry : a.y);
+        v[s] = mk<C>(hi ? b.x : rx, hi ? b.y : ry);
     }
 }
 template <typename C> __device__ __forceinline__ void transpose16_row(C *v, int j) {

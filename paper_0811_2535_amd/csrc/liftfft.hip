@@ -38,6 +38,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <map>
@@ -118,8 +119,10 @@ template <bool PERSIST> __device__ __forceinline__ int64_t tile_of(const PassArg
 // Largest workgroup: 1024 threads for complex64 with 16 values per thread;
 // 512 (up to 256 VGPRs per lane) for complex128, for 32 values per thread
 // and for persistent kernels, which hold the next tile in registers too.
+// (With a 1024-thread bound the 32-value kernels were held to 128 VGPRs and
+// spilled 130-180 bytes per lane.)
 template <typename Real, int EMAX, bool PERSIST> constexpr int max_threads() {
-    return sizeof(Real) == 4 && !PERSIST ? 1024 : 512;
+    return sizeof(Real) == 4 && EMAX == 16 && !PERSIST ? 1024 : 512;
 }
 // Minimum waves per SIMD the register allocation must allow: 8 (64 VGPRs,
 // two 1024-thread workgroups per CU) for the dense variants, else 1.
@@ -1011,7 +1014,7 @@ KernelFn pick_kernel(int dtype, int kind, int log2N, int rmax, const Variant &v)
 }
 
 int thread_cap(size_t esize, const Variant &v) {
-    return esize == 8 && !v.persist ? max_threads<float, 16, false>() : 512;
+    return esize == 8 && !v.persist && v.emax == 16 ? max_threads<float, 16, false>() : 512;
 }
 
 int ilog2_exact(int64_t v) {
@@ -1065,6 +1068,23 @@ struct fft_plan {
     };
     bool ragged = false;
     int length_classes = 0;
+    // Packed uneven batch, one plan per length class (the default form of
+    // fft_plan_create_many): each class is a single-length plan over its
+    // transforms' offsets, with its tables and scratch inside this plan's.
+    // Classes run on up to four streams -- the execute stream and three of
+    // the plan's own -- forked from and joined back into the execute
+    // stream, or replayed as one captured graph with those branches.
+    struct ClassRun {
+        fft_plan *sub;
+        int lane; // 0: the execute stream; k > 0: aux[k - 1]
+    };
+    std::vector<ClassRun> runs;
+    static constexpr int AUX = 3;
+    hipStream_t aux[AUX] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork_ev = nullptr, join_ev[AUX] = {nullptr, nullptr, nullptr};
+    int lanes = 1;
+    const int64_t *offsets = nullptr; // a class plan: first element of each of its transforms
+    int64_t packed_total = 0;         // a class plan: elements in the packed buffer
     // The paper's partitioned radix-2 plan (fft_plan_create_paper).
     bool paper = false;
     liftfft_paper::PaperPlan pp;
@@ -1282,6 +1302,15 @@ int launch(const fft_plan *p, const Launch &L, const PassArgs &args, hipStream_t
 
 void free_plan(fft_plan *p) {
     if (!p) return;
+    for (auto &r : p->runs) { // class plans: their device memory is this plan's
+        r.sub->tables = r.sub->scratch = nullptr;
+        free_plan(r.sub);
+    }
+    for (int k = 0; k < fft_plan::AUX; ++k) {
+        if (p->aux[k]) (void)hipStreamDestroy(p->aux[k]);
+        if (p->join_ev[k]) (void)hipEventDestroy(p->join_ev[k]);
+    }
+    if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
     for (auto &e : p->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &g : p->graphs) {
@@ -1334,8 +1363,42 @@ constexpr size_t MAX_GRAPHS = 16; // captured graphs kept per plan
 // an (in, out, sign) triple is seen and replayed afterwards.  When the
 // caller's stream is itself being captured, or the cache is full, the
 // kernels are launched directly.  `ev` (optional) brackets the work.
+int launch_plan(const fft_plan *p, const void *in, void *out, int sign, hipStream_t st);
+
+// Every class plan of a packed batch: forked from st onto the plan's
+// streams (classes of the same lane run in order) and joined back into st.
+int launch_classes(const fft_plan *p, const void *in, void *out, int sign, hipStream_t st) {
+    const hipStream_t lane[1 + fft_plan::AUX] = {st, p->aux[0], p->aux[1], p->aux[2]};
+    if (p->lanes > 1) {
+        if (hipEventRecord(p->fork_ev, st) != hipSuccess) return FFT_E_HIP;
+        for (int k = 1; k < p->lanes; ++k)
+            if (hipStreamWaitEvent(lane[k], p->fork_ev, 0) != hipSuccess) return FFT_E_HIP;
+    }
+    int rc = FFT_OK;
+    for (const auto &r : p->runs) {
+        rc = launch_plan(r.sub, in, out, sign, lane[r.lane]);
+        if (rc != FFT_OK) break;
+    }
+    for (int k = 1; k < p->lanes; ++k) // joined even after a failed launch
+        if (hipEventRecord(p->join_ev[k - 1], lane[k]) != hipSuccess ||
+            hipStreamWaitEvent(st, p->join_ev[k - 1], 0) != hipSuccess)
+            return FFT_E_HIP;
+    return rc;
+}
+
+// The work of a packed batch on stream st: the class plans, or the two
+// persistent launches and the single-pass classes (ev_mid, if given, is
+// recorded between the persistent passes).
+int packed_sequence(const fft_plan *p, const void *in, void *out, int sign, hipStream_t st, hipEvent_t ev_mid) {
+    if (!p->runs.empty()) {
+        const int rc = launch_classes(p, in, out, sign, st);
+        if (rc == FFT_OK && ev_mid) return hipEventRecord(ev_mid, st) == hipSuccess ? FFT_OK : FFT_E_HIP;
+        return rc;
+    }
+    return ragged_sequence(p, in, out, sign > 0, st, ev_mid);
+}
+
 int execute_ragged(const fft_plan *p, const void *in, void *out, int sign, hipStream_t st, const hipEvent_t *ev) {
-    const int inv = sign > 0;
     bool graph = p->use_graph;
     if (graph) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -1356,7 +1419,7 @@ int execute_ragged(const fft_plan *p, const void *in, void *out, int sign, hipSt
                 p->cap = nullptr;
             }
             if (p->cap && hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-                const int rc = ragged_sequence(p, in, out, inv, p->cap, nullptr);
+                const int rc = packed_sequence(p, in, out, sign, p->cap, nullptr);
                 hipGraph_t g = nullptr;
                 const bool ended = hipStreamEndCapture(p->cap, &g) == hipSuccess;
                 hipGraphExec_t e = nullptr;
@@ -1380,7 +1443,7 @@ int execute_ragged(const fft_plan *p, const void *in, void *out, int sign, hipSt
         }
     }
     if (ev && hipEventRecord(ev[0], st) != hipSuccess) return FFT_E_HIP;
-    int rc = ragged_sequence(p, in, out, inv, st, ev ? ev[1] : nullptr);
+    int rc = packed_sequence(p, in, out, sign, st, ev ? ev[1] : nullptr);
     if (rc == FFT_OK && ev) rc = hipEventRecord(ev[2], st) == hipSuccess ? FFT_OK : FFT_E_HIP;
     return rc;
 }
@@ -1618,6 +1681,130 @@ constexpr int STATIC_MAX_DEVICES = 64;
 std::mutex static_mutex;
 StaticDevice static_devices[STATIC_MAX_DEVICES];
 
+// Class plans of a packed batch (p: its lengths grouped by log2 length in
+// by_t as packed offsets; total elements, dtype, device set).  Each class is
+// shaped like fft_plan_create(2^t, count) -- or, with `tune`, like the
+// fastest configuration fft_plan_create_tuned finds for that shape -- and
+// addresses its transforms through a device list of offsets; the tables of
+// all classes share one allocation and the lifted classes one scratch array
+// with the packed layout.  Classes are dealt to four lanes (streams) by
+// decreasing size.
+int build_class_plans(fft_plan *p, const std::vector<std::vector<int64_t>> &by_t, bool tune) {
+    const int dtype = p->dtype;
+    struct Spec {
+        int t;
+        size_t first; // index of its first offset
+        int64_t count;
+    };
+    std::vector<Spec> specs;
+    std::vector<int64_t> offsets;
+    for (int t = int(by_t.size()) - 1; t >= 1; --t) { // longest first
+        if (by_t[t].empty()) continue;
+        specs.push_back({t, offsets.size(), int64_t(by_t[t].size())});
+        offsets.insert(offsets.end(), by_t[t].begin(), by_t[t].end());
+    }
+    p->length_classes = int(specs.size());
+    size_t table_bytes = 0;
+    bool lifted = false;
+    p->passes = 1;
+    for (const Spec &sp : specs) {
+        fft_plan *sub = new (std::nothrow) fft_plan;
+        if (!sub) return FFT_E_OOM;
+        p->runs.push_back({sub, 0});
+        fft_plan_opts o;
+        memset(&o, 0, sizeof(o));
+        if (tune) {
+            fft_plan *tp = nullptr;
+            fft_tune_result res;
+            const int rc = fft_plan_create_tuned(int64_t(1) << sp.t, sp.count, dtype, 16, &tp, &res);
+            if (rc != FFT_OK) return rc;
+            fft_plan_destroy(tp);
+            o = res.opts;
+        }
+        const int rc = shape_plan(sub, int64_t(1) << sp.t, sp.count, dtype, &o);
+        if (rc != FFT_OK) return rc;
+        table_bytes += (sub->table_bytes + 255) & ~size_t(255);
+        lifted = lifted || sub->passes >= 2;
+    }
+    p->passes = lifted ? 2 : 1; // timing: the whole batch, then an empty second interval
+    p->table_bytes = table_bytes;
+    if (hipMalloc(&p->tables, p->table_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p->tables = nullptr;
+        return FFT_E_OOM;
+    }
+    if (lifted) {
+        p->scratch_bytes = size_t(p->total) * p->esize;
+        if (hipMalloc(&p->scratch, p->scratch_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p->scratch = nullptr;
+            return FFT_E_OOM;
+        }
+    }
+    p->meta_bytes = offsets.size() * sizeof(int64_t);
+    if (hipMalloc(&p->meta, p->meta_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p->meta = nullptr;
+        return FFT_E_OOM;
+    }
+    if (hipMemcpy(p->meta, offsets.data(), p->meta_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        return FFT_E_HIP;
+    }
+    const int64_t *dev_offsets = static_cast<const int64_t *>(p->meta);
+    char *tb = static_cast<char *>(p->tables);
+    // Lanes: classes by decreasing bytes, each to the lane with the least
+    // work so far (lane 0 is the execute stream).
+    std::vector<size_t> order(specs.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    auto bytes = [&](size_t k) {
+        return (int64_t(1) << specs[k].t) * specs[k].count * int64_t(p->runs[k].sub->passes);
+    };
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return bytes(a) > bytes(b); });
+    const int lanes = int(specs.size()) < 1 + fft_plan::AUX ? int(specs.size()) : 1 + fft_plan::AUX;
+    std::vector<int64_t> load(lanes, 0);
+    for (size_t k : order) {
+        int best = 0;
+        for (int l = 1; l < lanes; ++l)
+            if (load[l] < load[best]) best = l;
+        p->runs[k].lane = best;
+        load[best] += bytes(k);
+    }
+    int rc = FFT_OK;
+    for (size_t k = 0; k < specs.size() && rc == FFT_OK; ++k) {
+        fft_plan *sub = p->runs[k].sub;
+        sub->tables = tb;
+        tb += (sub->table_bytes + 255) & ~size_t(255);
+        sub->scratch = sub->passes >= 2 ? p->scratch : nullptr;
+        sub->offsets = dev_offsets + specs[k].first;
+        sub->packed_total = p->total;
+        rc = fill_tables(sub, nullptr);
+    }
+    // Run in the order of the work list (longest lengths first), so that in
+    // each lane the large classes start first.
+    std::stable_sort(p->runs.begin(), p->runs.end(), [](const fft_plan::ClassRun &a, const fft_plan::ClassRun &b) {
+        return a.sub->n > b.sub->n;
+    });
+    if (rc == FFT_OK && hipDeviceSynchronize() != hipSuccess) rc = FFT_E_HIP;
+    if (rc != FFT_OK) return rc;
+    p->lanes = lanes;
+    if (lanes > 1) {
+        if (hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            p->fork_ev = nullptr;
+            return FFT_E_HIP;
+        }
+        for (int k = 0; k + 1 < lanes; ++k) {
+            if (hipStreamCreateWithFlags(&p->aux[k], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&p->join_ev[k], hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                return FFT_E_HIP;
+            }
+        }
+    }
+    return FFT_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -1754,7 +1941,8 @@ int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, uint3
     if (!lengths) return FFT_E_NULL;
     if (dtype != FFT_C64 && dtype != FFT_C128) return FFT_E_DTYPE;
     if (count < 1) return FFT_E_SIZE;
-    if (flags & ~uint32_t(FFT_OPT_GRAPH)) return FFT_E_ARG;
+    if (flags & ~uint32_t(FFT_OPT_GRAPH | FFT_OPT_PERSISTENT | FFT_OPT_AUTOTUNE)) return FFT_E_ARG;
+    if ((flags & FFT_OPT_PERSISTENT) && (flags & FFT_OPT_AUTOTUNE)) return FFT_E_ARG;
     const size_t esize = dtype == FFT_C64 ? 8 : 16;
     const int max_t = RAGGED_MAX_T, mline = max_line(dtype);
     // Lengths, packed offsets and the classes of equal length.
@@ -1794,6 +1982,12 @@ int fft_plan_create_many(const int64_t *lengths, int64_t count, int dtype, uint3
     if (hipGetDevice(&p->device) != hipSuccess) {
         (void)hipGetLastError();
         return fail(FFT_E_HIP);
+    }
+    if (!(flags & FFT_OPT_PERSISTENT)) {
+        const int rc = build_class_plans(p, by_t, (flags & FFT_OPT_AUTOTUNE) != 0);
+        if (rc != FFT_OK) return fail(rc);
+        *plan_out = p;
+        return FFT_OK;
     }
 
     // Twiddle tables: w_N^e for each line length used, and the two-level
@@ -2017,6 +2211,8 @@ int launch_plan(const fft_plan *p, const void *in, void *out, int sign, hipStrea
     a.log2q = p->log2q;
     a.log2h = p->log2h;
     a.dft_ops = p->dft_ops;
+    a.offsets = p->offsets;
+    a.total = p->packed_total;
     int rc = FFT_OK;
     const hipEvent_t *ev = nullptr;
     if (p->timing) {
@@ -2244,7 +2440,16 @@ int fft_plan_get_info(const fft_plan *p, fft_plan_info *info) {
         info->threads_pass3 = p->k3.threads;
         info->lds_bytes_pass3 = int64_t(p->k3.lds);
     }
-    if (p->ragged) {
+    if (p->ragged && !p->runs.empty()) {
+        info->lines_per_block_pass1 = info->lines_per_block_pass2 = 0;
+        info->grid_pass1 = info->grid_pass2 = 0;
+        info->threads_pass1 = info->threads_pass2 = 0;
+        info->lds_bytes_pass1 = info->lds_bytes_pass2 = 0;
+        info->variant_pass1 = info->variant_pass2 = 0;
+        info->length_classes = p->length_classes;
+        info->graph_launch = p->use_graph ? 1 : 0;
+        info->streams = p->lanes;
+    } else if (p->ragged) {
         info->lines_per_block_pass1 = info->lines_per_block_pass2 = 0;
         info->grid_pass1 = int32_t(p->ra.grid);
         info->grid_pass2 = int32_t(p->rb.grid);

@@ -288,8 +288,8 @@ def test_scratch_slab_widths(lf, t, batch):
     per thread in pass 2 (split exchange), against the oracle."""
     x = datagen.signals(1 << t, batch, np.complex64, "normal", 330 + t)
     ref = oracle.fft_batch(x.astype(np.complex128), -1)
-    for W, vpt2, T1, T2 in ((1, 0, 2, 4), (4, 0, 2, 4), (8, 0, 2, 4), (8, 32, 2, 8), (16, 32, 4, 8),
-                            (2, 32, 4, 8)):
+    for W, vpt2, T1, T2 in ((1, 0, 2, 4), (4, 0, 2, 4), (8, 0, 2, 4), (8, 32, 2, 4), (16, 32, 4, 4),
+                            (2, 32, 4, 2)):
         announce("slab width W=%d vpt2=%d T=(%d,%d) n=2^%d" % (W, vpt2, T1, T2, t))
         got = run_plan(lf, x, -1, scratch_width=W, values_per_thread2=vpt2, lines_per_block=T1,
                        lines_per_block2=T2, flags=2)

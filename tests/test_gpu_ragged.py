@@ -41,10 +41,10 @@ def oracle_ragged(x, lengths, sign):
     return out
 
 
-def run_ragged(lf, x_np, lengths, sign, graph=False, repeat=1):
+def run_ragged(lf, x_np, lengths, sign, graph=False, repeat=1, persistent=False, autotune=False):
     import torch
     dt = torch.complex64 if x_np.dtype == np.complex64 else torch.complex128
-    plan = lf.Plan.uneven(lengths, dt, graph=graph)
+    plan = lf.Plan.uneven(lengths, dt, graph=graph, persistent=persistent, autotune=autotune)
     x = to_dev(x_np)
     outs = []
     for _ in range(repeat):
@@ -66,8 +66,13 @@ def check_ragged(got, ref, lengths, tol, what):
     return max(errs)
 
 
+FORMS = [False, True]  # class plans on forked streams (default); persistent launches
+FORM_IDS = ["classes", "persistent"]
+
+
+@pytest.mark.parametrize("persistent", FORMS, ids=FORM_IDS)
 @pytest.mark.parametrize("dtype", [np.complex64, np.complex128], ids=["c64", "c128"])
-def test_every_length_class(lf, dtype):
+def test_every_length_class(lf, dtype, persistent):
     """Every length 2^1..2^16 (single-pass classes up to 2^14 complex64 /
     2^13 complex128, lifted ones above) in one packed batch with random extra
     lengths, both signs."""
@@ -75,32 +80,38 @@ def test_every_length_class(lf, dtype):
     lengths = [1 << int(k) for k in ks]
     x = datagen.ragged_signals(lengths, dtype, "uniform", 32)
     for sign in (-1, 1):
-        announce("ragged every-class %s sign=%d count=%d" % (np.dtype(dtype).name, sign, len(lengths)))
-        got, info = run_ragged(lf, x, lengths, sign)
+        announce("ragged every-class %s sign=%d count=%d persistent=%d"
+                 % (np.dtype(dtype).name, sign, len(lengths), persistent))
+        got, info = run_ragged(lf, x, lengths, sign, persistent=persistent)
         assert info["length_classes"] == 16 and info["passes"] == 2
+        assert info["streams"] == (0 if persistent else 4)
         check_ragged(got, oracle_ragged(x, lengths, sign), lengths, TOL[dtype], ("classes", sign))
 
 
-def test_config3_full(lf):
+@pytest.mark.parametrize("persistent", FORMS, ids=FORM_IDS)
+def test_config3_full(lf, persistent):
     """4096 transforms with k ~ U{8..16} (seed 3), complex64, U[-1,1]: the
     whole batch against the oracle, forward and inverse."""
     ks = datagen.uneven_log2_lengths(4096, 8, 16, seed=3)
     lengths = [1 << int(k) for k in ks]
     x = datagen.ragged_signals(lengths, np.complex64, "uniform", 3)
     for sign in (-1, 1):
-        announce("ragged config3 sign=%d elements=%d" % (sign, len(x)))
-        got, info = run_ragged(lf, x, lengths, sign)
+        announce("ragged config3 sign=%d elements=%d persistent=%d" % (sign, len(x), persistent))
+        got, info = run_ragged(lf, x, lengths, sign, persistent=persistent)
         assert info["length_classes"] == 9 and info["graph_launch"] == 0
         check_ragged(got, oracle_ragged(x, lengths, sign), lengths, 1e-6, ("config3", sign))
 
 
-def test_long_transforms_in_batch(lf):
-    """Lifted lengths up to 2^22 mixed with short ones, and a batch whose only
-    length is lifted (no single-pass class)."""
-    for lengths in ([1 << 22, 256, 1 << 13, 2, 1 << 20, 1 << 13], [1 << 18, 1 << 18]):
+@pytest.mark.parametrize("persistent", FORMS, ids=FORM_IDS)
+def test_long_transforms_in_batch(lf, persistent):
+    """Lifted lengths up to 2^24 (the three-level lift in the class form)
+    mixed with short ones, and a batch whose only length is lifted (no
+    single-pass class)."""
+    for lengths in ([1 << 22, 256, 1 << 13, 2, 1 << 20, 1 << 13], [1 << 18, 1 << 18],
+                    [1 << 24, 1 << 10, 1 << 16]):
         x = datagen.ragged_signals(lengths, np.complex64, "normal", 41)
-        announce("ragged long %s" % (lengths,))
-        got, _ = run_ragged(lf, x, lengths, -1)
+        announce("ragged long %s persistent=%d" % (lengths, persistent))
+        got, _ = run_ragged(lf, x, lengths, -1, persistent=persistent)
         check_ragged(got, oracle_ragged(x, lengths, -1), lengths, 1e-6, lengths)
 
 
@@ -113,15 +124,17 @@ def test_only_short_transforms(lf):
     check_ragged(got, oracle_ragged(x, lengths, 1), lengths, 1e-12, "short")
 
 
-def test_graph_replays_match_direct_launches(lf, torch):
+@pytest.mark.parametrize("persistent", FORMS, ids=FORM_IDS)
+def test_graph_replays_match_direct_launches(lf, torch, persistent):
     """Graph replays (several, with eager work and synchronisations between
     them) give exactly the result of direct launches, for both signs and two
-    buffer pairs."""
+    buffer pairs; in the class form the graph holds the classes' streams as
+    parallel branches."""
     ks = datagen.uneven_log2_lengths(300, 4, 15, seed=43)
     lengths = [1 << int(k) for k in ks]
     x_np = datagen.ragged_signals(lengths, np.complex64, "uniform", 43)
-    direct = {s: run_ragged(lf, x_np, lengths, s, graph=False)[0] for s in (-1, 1)}
-    plan = lf.Plan.uneven(lengths, torch.complex64, graph=True)
+    direct = {s: run_ragged(lf, x_np, lengths, s, graph=False, persistent=persistent)[0] for s in (-1, 1)}
+    plan = lf.Plan.uneven(lengths, torch.complex64, graph=True, persistent=persistent)
     xs = [to_dev(x_np), to_dev(x_np)]
     ys = [torch.empty_like(xs[0]), torch.empty_like(xs[0])]
     for rep in range(4):
@@ -178,3 +191,15 @@ def test_ragged_timing_and_errors(lf, torch):
     with pytest.raises(lf.FFTError):
         plan.execute(x, y, 0)
     plan.destroy()
+
+
+def test_autotuned_classes(lf, torch):
+    """FFT_OPT_AUTOTUNE: every class shaped by the tuner (16 candidates per
+    shape), both signs, against the oracle."""
+    lengths = [1 << 16] * 3 + [1 << 10] * 20 + [1 << 19] * 2 + [64] * 9
+    x = datagen.ragged_signals(lengths, np.complex64, "normal", 45)
+    for sign in (-1, 1):
+        announce("ragged autotuned classes sign=%d" % sign)
+        got, info = run_ragged(lf, x, lengths, sign, autotune=True)
+        assert info["length_classes"] == 4
+        check_ragged(got, oracle_ragged(x, lengths, sign), lengths, 1e-6, ("autotune", sign))
