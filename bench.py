@@ -780,6 +780,9 @@ def main() -> int:
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary from two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of this benchmark and exit")
+    ap.add_argument("--only", choices=["config1", "fwd_bwd", "ragged", "precision"],
+                    help="run one of the extra measurements alone (for a kernel trace of it) and print "
+                         "its JSON object")
     ap.add_argument("--summarize-trace", metavar="KERNEL_STATS_CSV",
                     help="print a markdown table of a rocprofv3 --kernel-trace --stats summary of this "
                          "benchmark (run_kernel_stats.csv) and exit")
@@ -824,6 +827,12 @@ def main() -> int:
     lf.lib()  # fail loudly if the HIP library is missing
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.only:
+        fn = {"config1": measure_config1, "fwd_bwd": measure_fwd_bwd, "ragged": measure_ragged,
+              "precision": measure_precision}[args.only]
+        res, _ = fn(torch, lf, datagen)
+        print(json.dumps({args.only: res}), flush=True)
+        return 0
     if args.sweep:
         return run_sweep(torch, lf, args.log2n)
     if args.sweep_lifts:
