@@ -677,6 +677,17 @@ def run_sweep(torch, lf, log2n: int, sets: int = 4, reps: int = 12) -> int:
         torch.neg(xs[(i + 1) % sets], out=ys[i % sets])
         torch.neg(ys[i % sets], out=tmp)
     emit({"reference": "two torch.neg in a chain, the second reading what the first wrote", "us": timeit(chain)})
+    if log2n % 2 == 0:
+        # Each pass's permutation of the elements without its arithmetic, as
+        # torch copies (the kernel torch picks traverses the output in order).
+        P = Q = 1 << (log2n // 2)
+        emit({"reference": "pass 1's element movement x[j1 + p k2] -> S[j1/2][k2][j1%%2] (16-byte pairs "
+                           "transposed, p = q = %d), torch copy_" % P,
+              "us": timeit(lambda i: ys[i % sets].view(P // 2, Q, 2).copy_(
+                  xs[(i + 1) % sets].view(Q, P // 2, 2).transpose(0, 1)))})
+        emit({"reference": "pass 2's element movement S[k1/2][k2][k1%2] -> X[k2 + q k1], torch copy_",
+              "us": timeit(lambda i: ys[i % sets].view(P // 2, 2, Q).copy_(
+                  xs[(i + 1) % sets].view(P // 2, Q, 2).permute(0, 2, 1)))})
 
     def plan_times(label, **kw):
         try:
@@ -705,6 +716,7 @@ def run_sweep(torch, lf, log2n: int, sets: int = 4, reps: int = 12) -> int:
     TWO, THREE = B.FFT_OPT_TWO_LEVEL, B.FFT_OPT_THREE_LEVEL
     SPLIT, FULL = B.FFT_OPT_SPLIT_EXCHANGE, B.FFT_OPT_FULL_EXCHANGE
     plan_times("two-level default", flags=TWO)
+    plan_times("two-level, pass 1 staged in LDS by direct loads", flags=TWO | B.FFT_OPT_LDS_PREFETCH)
     plan_times("three-level default", flags=THREE)
     plan_times("three-level shuffle exchange", flags=THREE | B.FFT_OPT_SHUFFLE_EXCHANGE)
     plan_times("three-level split exchange", flags=THREE | SPLIT)
@@ -719,6 +731,11 @@ def run_sweep(torch, lf, log2n: int, sets: int = 4, reps: int = 12) -> int:
             for fl, fn in ((SPLIT, "split"), (FULL, "complex")):
                 plan_times("pass 2 T=%d, %d values/thread, %s exchange" % (T2, vpt, fn), flags=TWO | fl,
                            lines_per_block=2, lines_per_block2=T2, values_per_thread=16, values_per_thread2=vpt)
+    for W in (1, 4, 8):
+        plan_times("two-level, scratch slabs %d wide" % W, flags=TWO | SPLIT, lines_per_block=2,
+                   lines_per_block2=4, scratch_width=W)
+    plan_times("two-level, scratch slabs 8 wide, pass 2 32 values/thread", flags=TWO | SPLIT, lines_per_block=2,
+               lines_per_block2=4, scratch_width=8, values_per_thread2=32)
     for flags, fn in ((B.FFT_OPT_PERSISTENT, "persistent"), (B.FFT_OPT_DENSE | SPLIT, "dense split")):
         plan_times("two-level %s" % fn, flags=TWO | flags)
     for lp in (10, 11, 13, 14):

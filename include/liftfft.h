@@ -126,6 +126,15 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out);
  *                     keep the default kernel; FFT_E_UNSUPPORTED when no
  *                     pass has 256-point lines or the type is complex128;
  *                     other kernel-variant options: FFT_E_ARG).
+ *                     FFT_OPT_LDS_PREFETCH (with FFT_OPT_TWO_LEVEL only):
+ *                     pass 1 over 4096-point complex64 columns (2 per
+ *                     tile) as one persistent workgroup per CU that stages
+ *                     its next tile in LDS with direct global-to-LDS loads
+ *                     while transforming the current one; other shapes
+ *                     return FFT_E_UNSUPPORTED, other kernel-variant
+ *                     options FFT_E_ARG.  Inputs not 16-byte aligned run
+ *                     the plain pass 1.  A measured alternative: slower
+ *                     than the default pass 1 at n = 2^24.
  *                     FFT_OPT_THREE_LEVEL takes no two-level options
  *                     (log2_p, lines_per_block2, values_per_thread2,
  *                     scratch_width: FFT_E_ARG); lines_per_block then sets
@@ -167,7 +176,8 @@ enum {
     FFT_OPT_DENSE = 32,
     FFT_OPT_TWO_LEVEL = 128,
     FFT_OPT_THREE_LEVEL = 256,
-    FFT_OPT_SHUFFLE_EXCHANGE = 512
+    FFT_OPT_SHUFFLE_EXCHANGE = 512,
+    FFT_OPT_LDS_PREFETCH = 2048
 };
 typedef struct fft_plan_opts {
     int32_t log2_p;
@@ -310,7 +320,8 @@ const char *fft_strerror(int code);
  *   variant_pass1/2            kernel variant bits: 1 = 32 values per
  *                              thread, 2 = split exchange, 4 = persistent,
  *                              8 = dense (64-VGPR cap), 16/32 = the
- *                              matrix-core forms, 64 = shuffle exchange
+ *                              matrix-core forms, 64 = shuffle exchange,
+ *                              128 = LDS-staged pass 1
  *   precision                  FFT_PREC_* set by fft_plan_set_precision
  *   length_classes, graph_launch  plans of uneven lengths: number of
  *                              distinct lengths, and whether executes replay

@@ -335,7 +335,18 @@ __device__ __forceinline__ void fill_twiddles(C *twl, const C *__restrict__ tw, 
 //   twl    the LDS twiddle tables
 // The first LDS write happens without a barrier: the caller orders it after
 // any earlier readers of the tile.
-template <typename C, int N, int RMAX, int E, bool SPLIT, int STG = 0>
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS
+// operations, then for every wave, without the memory fence of
+// __syncthreads (which would also wait for outstanding global loads, among
+// them direct-to-LDS loads still streaming the next tile).
+__device__ __forceinline__ void lds_barrier() { __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+template <bool LDS_ONLY> __device__ __forceinline__ void tile_barrier() {
+    if constexpr (LDS_ONLY) lds_barrier();
+    else __syncthreads();
+}
+
+template <typename C, int N, int RMAX, int E, bool SPLIT, int STG = 0, bool LDS_ONLY = false>
 __device__ __forceinline__ void run_stages(C *v, void *line_base, const C *twl, int j) {
     using Real = decltype(C::x);
     constexpr int TPL = N / E;
@@ -364,7 +375,7 @@ __device__ __forceinline__ void run_stages(C *v, void *line_base, const C *twl, 
         constexpr int R2 = sched_radix(N, RMAX, STG + 1), NB2 = E / R2;
         if constexpr (!SPLIT) {
             C *line = static_cast<C *>(line_base);
-            if constexpr (STG > 0) __syncthreads(); // earlier readers of the tile are done
+            if constexpr (STG > 0) tile_barrier<LDS_ONLY>(); // earlier readers of the tile are done
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
                 const int b = j + i * TPL;
@@ -372,7 +383,7 @@ __device__ __forceinline__ void run_stages(C *v, void *line_base, const C *twl, 
 #pragma unroll
                 for (int r = 0; r < R; ++r) line[lpad<N>(base + r * NS)] = v[i * R + r];
             }
-            __syncthreads();
+            tile_barrier<LDS_ONLY>();
 #pragma unroll
             for (int i = 0; i < NB2; ++i) {
                 const int b = j + i * TPL;
@@ -385,7 +396,7 @@ __device__ __forceinline__ void run_stages(C *v, void *line_base, const C *twl, 
             Real *line = static_cast<Real *>(line_base);
 #pragma unroll
             for (int part = 0; part < 2; ++part) {
-                if (STG > 0 || part > 0) __syncthreads();
+                if (STG > 0 || part > 0) tile_barrier<LDS_ONLY>();
 #pragma unroll
                 for (int i = 0; i < NB; ++i) {
                     const int b = j + i * TPL;
@@ -394,7 +405,7 @@ __device__ __forceinline__ void run_stages(C *v, void *line_base, const C *twl, 
                     for (int r = 0; r < R; ++r)
                         line[lpad<N>(base + r * NS)] = part ? v[i * R + r].y : v[i * R + r].x;
                 }
-                __syncthreads();
+                tile_barrier<LDS_ONLY>();
 #pragma unroll
                 for (int i = 0; i < NB2; ++i) {
                     const int b = j + i * TPL;
@@ -407,7 +418,7 @@ __device__ __forceinline__ void run_stages(C *v, void *line_base, const C *twl, 
                 }
             }
         }
-        run_stages<C, N, RMAX, E, SPLIT, STG + 1>(v, line_base, twl, j);
+        run_stages<C, N, RMAX, E, SPLIT, STG + 1, LDS_ONLY>(v, line_base, twl, j);
     }
 }
 

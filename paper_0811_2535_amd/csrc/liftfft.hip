@@ -748,6 +748,117 @@ __global__ __launch_bounds__(SHUF_THREADS) void axis_shuffle_kernel(PassArgs a) 
 }
 
 // ---------------------------------------------------------------------------
+// Pass 1 of the two-level lift with the next tile staged in LDS by direct
+// global-to-LDS loads (gfx950 global_load_lds_dwordx4), for complex64 columns
+// of 4096 points, 2 columns per tile.  One persistent workgroup per CU walks
+// its tiles; while tile k is transformed in registers (its stage exchange in
+// the LDS buffer it arrived in), tile k+1 streams into the other buffer
+// without occupying registers.  Row r of a staged tile is the 16-byte pair of
+// the tile's two columns at row r.  Barriers inside the loop wait for LDS
+// only (lds_barrier): a workgroup barrier with a memory fence would also wait
+// for the staged loads in flight.  One wait for vector memory per tile, after
+// the transform and before the stores: it covers the next tile's staged
+// loads and the previous tile's stores, both issued a whole transform
+// earlier.  The next tile's weight inputs are loaded just before that wait
+// (a register load waited for later would also wait for what was issued
+// after it), and the transform's base is computed, not loaded.
+constexpr int DMA_N = 4096, DMA_T = 2, DMA_THREADS = 512, DMA_E = 16, DMA_TPL = DMA_N / DMA_E;
+constexpr int DMA_ROWS_PER_OP = 64, DMA_WAVES = DMA_THREADS / 64;
+constexpr int DMA_OPS = DMA_N / (DMA_ROWS_PER_OP * DMA_WAVES); // per wave per tile
+constexpr int DMA_EP = DMA_T * (DMA_E + 1);
+
+// Wait for every vector memory operation of this wave (the staged tile's
+// direct-to-LDS loads among them).
+__device__ __forceinline__ void wait_vmem() { __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+__global__ __launch_bounds__(DMA_THREADS, 1) void pass1_dma_kernel(PassArgs a) {
+    using C = float2;
+    constexpr uint32_t ES = sizeof(C);
+    __shared__ float4 buf0[DMA_N], buf1[DMA_N];
+    __shared__ C twl[tw_total(DMA_N, 16)];
+    __shared__ C ep[2][DMA_EP];
+    const int tid = threadIdx.x, c = tid & (DMA_T - 1), j = tid >> 1;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const C *__restrict__ in = static_cast<const C *>(a.in);
+    C *__restrict__ out = static_cast<C *>(a.out);
+    const int64_t pmask = (int64_t(1) << a.log2p) - 1;
+    const int64_t P = int64_t(1) << a.log2p;
+    const float sin_ = a.conj_in ? -1.f : 1.f;
+    const C *__restrict__ hi = static_cast<const C *>(a.tw_hi);
+    const C *__restrict__ lo = static_cast<const C *>(a.tw_lo);
+    const uint32_t lomask = (1u << a.log2h) - 1, nmask = uint32_t(a.n - 1);
+    // Stage `t`'s rows into `dst`: wave w's op i covers rows (8i + w)*64 + lane.
+    auto stage = [&](int64_t t, float4 *dst) {
+        const int64_t line0 = t * DMA_T, b = line0 >> a.log2p, j10 = line0 & pmask;
+        const C *col = in + b * a.n + j10; // single-length plans only (no packed offsets)
+#pragma unroll
+        for (int i = 0; i < DMA_OPS; ++i) {
+            const int row0 = (i * DMA_WAVES + wave) * DMA_ROWS_PER_OP;
+            __builtin_amdgcn_global_load_lds(col + int64_t(row0 + lane) * P, dst + row0, 16, 0, 0);
+        }
+    };
+    // Weight inputs of tile `t`: this thread's base entry w^(j1 * j) and, for
+    // the first DMA_EP threads, the per-row factors w^(j1 * 256 s) (last slot
+    // of each column unused).
+    const int ei = tid < DMA_EP ? tid : 0;
+    const int ec = ei / (DMA_E + 1), es = ei - ec * (DMA_E + 1);
+    const bool ep_writer = tid < DMA_EP && es < DMA_E;
+    C ahi, alo, phi, plo;
+    auto load_weights = [&](int64_t t) {
+        const int64_t j10 = (t * DMA_T) & pmask;
+        const uint32_t xa = (uint32_t(j10 + c) * uint32_t(j)) & nmask;
+        const uint32_t xp = es < DMA_E ? (uint32_t(j10 + ec) * uint32_t(es * DMA_TPL)) & nmask : 0u;
+        ahi = hi[xa >> a.log2h];
+        alo = lo[xa & lomask];
+        phi = hi[xp >> a.log2h];
+        plo = lo[xp & lomask];
+    };
+    int64_t t = tile_of<true>(a, 0);
+    if (t < 0) return; // workgroup-uniform
+    stage(t, buf0);
+    fill_twiddles<C, DMA_N, 16>(twl, static_cast<const C *>(a.tw), tid, DMA_THREADS);
+    load_weights(t);
+    wait_vmem();
+    lds_barrier(); // the first staged tile and twl are in LDS
+    C A = cmul(ahi, alo);
+    if (ep_writer) ep[0][tid] = cmul(phi, plo);
+    for (int64_t k = 0;; ++k) {
+        float4 *cur = (k & 1) ? buf1 : buf0, *nxt = (k & 1) ? buf0 : buf1;
+        const int64_t line0 = t * DMA_T, b = line0 >> a.log2p, j10 = line0 & pmask;
+        C v[DMA_E];
+        const float2 *rows = reinterpret_cast<const float2 *>(cur);
+#pragma unroll
+        for (int s = 0; s < DMA_E; ++s) v[s] = scale_im(rows[2 * (j + s * DMA_TPL) + c], sin_);
+        // Every wave has read `cur` (it becomes this tile's exchange array) and
+        // finished the previous tile (its exchange array `nxt` is free); this
+        // tile's ep entries are published.
+        lds_barrier();
+        const int64_t tn = tile_of<true>(a, k + 1);
+        if (tn >= 0) stage(tn, nxt);
+        float *xline = reinterpret_cast<float *>(cur) + c * a.pitch;
+        run_stages<C, DMA_N, 16, DMA_E, true, 0, true>(v, xline, twl, j);
+        if (tn >= 0) load_weights(tn);
+        wait_vmem();
+        lds_barrier(); // the next tile is staged (every wave's part)
+        C An = cmul(ahi, alo);
+        // Keep the weight products ahead of the stores: a use of the loaded
+        // weights placed among the stores would wait for the stores before it.
+        __asm__ volatile("" : "+v"(An.x), "+v"(An.y));
+        if (tn >= 0 && ep_writer) ep[(k + 1) & 1][tid] = cmul(phi, plo);
+        // Store into the scratch slabs S[j1/2][k2][j1%2] (slab width 2 = T).
+        const rsrc_t dst = make_rsrc(out + b * a.n + (j10 << a.log2q), uint32_t(DMA_T << a.log2q) * ES);
+        const uint32_t lane_off = ((uint32_t(j) << 1) + uint32_t(c)) * ES;
+        const C *Pc = ep[k & 1] + c * (DMA_E + 1);
+#pragma unroll
+        for (int s = 0; s < DMA_E; ++s)
+            buf_store(cmulc(v[s], cmul(A, Pc[s])), dst, lane_off, (uint32_t(s * DMA_TPL) << 1) * ES);
+        if (tn < 0) break;
+        A = An;
+        t = tn;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Packed batches of uneven power-of-two lengths.  The plan groups the
 // transforms into classes of equal length.  Lengths up to 2^12 run through
 // the single-pass kernel, one launch per class, with `a.offsets` listing
@@ -900,10 +1011,13 @@ struct Variant {
     bool dense = false;   // 64-VGPR cap (two 1024-thread workgroups per CU)
     int prec = 0;         // PREC_*: radix-16 stages on the matrix cores when nonzero
     bool shuffle = false; // axis passes: stage exchange by wavefront shuffles
-    bool is_default() const { return emax == 16 && !split && !persist && !dense && !prec && !shuffle; }
+    bool lds_prefetch = false; // pass 1: persistent, next tile staged in LDS by direct loads
+    bool is_default() const {
+        return emax == 16 && !split && !persist && !dense && !prec && !shuffle && !lds_prefetch;
+    }
     int code() const {
         return (emax == 32 ? 1 : 0) | (split ? 2 : 0) | (persist ? 4 : 0) | (dense ? 8 : 0) | (prec << 4) |
-               (shuffle ? 64 : 0);
+               (shuffle ? 64 : 0) | (lds_prefetch ? 128 : 0);
     }
 };
 
@@ -996,6 +1110,11 @@ KernelFn pick_kernel(int dtype, int kind, int log2N, int rmax, const Variant &v)
                                     : pick_mfma_kind<PREC_BF16X2>(kind, log2N);
     }
     if (kind == K_AXIS_WIDE && !v.is_default()) return nullptr;
+    if (v.lds_prefetch) { // complex64 pass 1 over 4096-point columns, 2 per tile, split exchange
+        if (kind != K_PASS1 || dtype != FFT_C64 || rmax != 16 || log2N != 12 || v.code() != (128 | 2))
+            return nullptr;
+        return &pass1_dma_kernel;
+    }
     if (v.shuffle) { // complex64 axis passes over 256-point lines
         if (kind != K_AXIS || dtype != FFT_C64 || rmax != 16 || log2N != 8 || v.code() != 64) return nullptr;
         return &axis_shuffle_kernel;
@@ -1049,6 +1168,7 @@ struct fft_plan {
     size_t table_bytes = 0;
     const void *tw1 = nullptr, *tw2 = nullptr, *tw_hi = nullptr, *tw_lo = nullptr;
     Launch k1, k2, k3; // k3: third pass of a three-level lift
+    Launch k1_plain;   // pass 1 for inputs the LDS-staged pass 1 cannot load (not 16-byte aligned)
     int log2n1 = 0, log2n2 = 0, log2n3 = 0; // three-level lift n = n1 n2 n3 (n1 contiguous)
     const void *tw3 = nullptr;
     Variant base1, base2, base3; // the variants chosen at creation (precision FP32)
@@ -1187,13 +1307,17 @@ bool fill_launch(Launch &L, int dtype, int kind, int log2N, int rmax, int log2T,
         if ((int64_t(1) << log2T) != SHUF_T || L.threads != SHUF_THREADS) return false;
         L.lds = 0;
     }
+    if (v.lds_prefetch) { // fixed shape: 2 columns of 4096 points, static LDS
+        if ((int64_t(1) << log2T) != DMA_T || L.threads != DMA_THREADS) return false;
+        L.lds = 0;
+    }
     if (L.lds > 65536 &&
         hipFuncSetAttribute(reinterpret_cast<const void *>(L.fn),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(L.lds)) != hipSuccess) {
         (void)hipGetLastError();
         return false;
     }
-    if (!v.persist) {
+    if (!v.persist && !v.lds_prefetch) {
         L.grid = L.ntiles;
         L.remap = (L.grid % 8 == 0) && L.grid >= 16;
     } else {
@@ -1520,7 +1644,14 @@ int shape_plan(fft_plan *p, int64_t n, int64_t batch, int dtype, const fft_plan_
     if (o.lines_per_block2 < 0 || (o.lines_per_block2 & (o.lines_per_block2 - 1))) return FFT_E_ARG;
     constexpr int32_t known_flags = FFT_OPT_NO_XCD_REMAP | FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE |
                                     FFT_OPT_PERSISTENT | FFT_OPT_ONE_TILE | FFT_OPT_DENSE |
-                                    FFT_OPT_TWO_LEVEL | FFT_OPT_THREE_LEVEL | FFT_OPT_SHUFFLE_EXCHANGE;
+                                    FFT_OPT_TWO_LEVEL | FFT_OPT_THREE_LEVEL | FFT_OPT_SHUFFLE_EXCHANGE |
+                                    FFT_OPT_LDS_PREFETCH;
+    // the staged pass 1 is a two-level variant of its own
+    if ((o.flags & FFT_OPT_LDS_PREFETCH) &&
+        (!(o.flags & FFT_OPT_TWO_LEVEL) || (o.flags & (FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE |
+                                                         FFT_OPT_PERSISTENT | FFT_OPT_DENSE)) ||
+         o.values_per_thread || o.scratch_width || (o.lines_per_block && o.lines_per_block != 2)))
+        return FFT_E_ARG;
     // the shuffle exchange exists for three-level plans only, as the only variant
     if ((o.flags & FFT_OPT_SHUFFLE_EXCHANGE) &&
         (!(o.flags & FFT_OPT_THREE_LEVEL) || (o.flags & (FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE |
@@ -1640,6 +1771,18 @@ int shape_plan(fft_plan *p, int64_t n, int64_t batch, int dtype, const fft_plan_
             return FFT_E_UNSUPPORTED;
         }
         p->log2W = o.scratch_width ? ilog2_exact(o.scratch_width) : p->k1.log2T;
+        if (o.flags & FFT_OPT_LDS_PREFETCH) {
+            // Pass 1 with the next tile staged in LDS: 4096-point complex64
+            // columns, 2 per tile, slabs of width 2.  The plain pass-1 launch
+            // stays for inputs not 16-byte aligned.
+            Variant vd;
+            vd.split = true;
+            vd.lds_prefetch = true;
+            p->k1_plain = p->k1;
+            if (dtype != FFT_C64 || radix != 16 || p->log2q != 12 || p->log2W != 1 || p->k1.log2T != 1 ||
+                !fill_launch(p->k1, dtype, K_PASS1, 12, 16, 1, P * batch, vd, p->device))
+                return FFT_E_UNSUPPORTED;
+        }
     }
     p->no_remap = (o.flags & FFT_OPT_NO_XCD_REMAP) != 0;
     apply_remap_policy(p);
@@ -2280,20 +2423,24 @@ int launch_plan(const fft_plan *p, const void *in, void *out, int sign, hipStrea
             if (rc == FFT_OK && ev) rc = hipEventRecord(ev[k + 1], st) == hipSuccess ? FFT_OK : FFT_E_HIP;
         }
     } else {
+        // The LDS-staged pass 1 loads 16-byte row pairs: other inputs take
+        // the plain pass-1 kernel.
+        const Launch &K1 =
+            p->k1.var.lds_prefetch && (reinterpret_cast<uintptr_t>(in) & 15) ? p->k1_plain : p->k1;
         a.in = in;
         a.out = p->scratch;
         a.tw = p->tw1;
         a.tw_hi = p->tw_hi;
         a.tw_lo = p->tw_lo;
-        a.lines = p->k1.lines;
-        a.ntiles = p->k1.ntiles;
-        a.pitch = p->k1.pitch;
-        a.log2T = p->k1.log2T;
+        a.lines = K1.lines;
+        a.ntiles = K1.ntiles;
+        a.pitch = K1.pitch;
+        a.log2T = K1.log2T;
         a.log2T1 = p->log2W;
         a.conj_in = inv;
         a.conj_out = 0;
-        a.xcd_remap = p->k1.remap;
-        if (rc == FFT_OK) rc = launch(p, p->k1, a, st);
+        a.xcd_remap = K1.remap;
+        if (rc == FFT_OK) rc = launch(p, K1, a, st);
         if (rc == FFT_OK && ev) rc = hipEventRecord(ev[1], st) == hipSuccess ? FFT_OK : FFT_E_HIP;
         a.in = p->scratch;
         a.out = out;

@@ -310,3 +310,38 @@ def test_complex128_repeat_determinism(lf, torch):
         for k in range(1, reps):
             assert np.array_equal(outs[k].view(np.uint64), outs[0].view(np.uint64)), (t, k)
         check_rows(outs[0], x_np, 1, TOL[np.complex128])
+
+
+LDS_PREFETCH = 2048  # FFT_OPT_LDS_PREFETCH
+
+
+@pytest.mark.parametrize("t,batch", [(24, 1), (23, 2)])
+def test_lds_staged_pass1(lf, torch, t, batch):
+    """Pass 1 with the next tile staged in LDS by direct global-to-LDS loads
+    (4096-point columns, persistent workgroups): against the oracle for both
+    signs, against the default plan to rounding level, in place, and for an
+    input that is only 8-byte aligned (which takes the plain pass 1)."""
+    x = datagen.signals(1 << t, batch, np.complex64, "normal", 340 + t)
+    plan = lf.Plan(1 << t, batch, torch.complex64, flags=128 | LDS_PREFETCH)
+    info = plan.info()
+    plan.destroy()
+    assert info["variant_pass1"] & 128 and info["lines_per_block_pass1"] == 2, info
+    for sign in (-1, 1):
+        announce("lds-staged pass 1 n=2^%d batch=%d sign=%d" % (t, batch, sign))
+        got = run_plan(lf, x, sign, flags=128 | LDS_PREFETCH)
+        check_rows(got, x, sign, TOL[np.complex64])
+        assert_rounding_level(got, run_plan(lf, x, sign, flags=128), ("lds-staged", t, sign))
+    announce("lds-staged pass 1 n=2^%d in place and 8-byte aligned input" % t)
+    n = 1 << t
+    plan = lf.Plan(n, batch, torch.complex64, flags=128 | LDS_PREFETCH)
+    xd = to_dev(x)
+    plan.execute(xd, xd, -1)
+    buf = torch.zeros(n * batch + 1, dtype=torch.complex64, device="cuda")
+    shifted = buf[1:].view(batch, n)  # 8 bytes past a 16-byte boundary
+    shifted.copy_(to_dev(x))
+    y = torch.empty_like(shifted)
+    plan.execute(shifted, y, -1)
+    torch.cuda.synchronize()
+    plan.destroy()
+    check_rows(to_np(xd), x, -1, TOL[np.complex64])
+    check_rows(to_np(y), x, -1, TOL[np.complex64])
