@@ -464,9 +464,11 @@ template <typename C> __device__ __forceinline__ void transpose16_row(C *v, int 
 // ---------------------------------------------------------------------------
 // Precision forms on the matrix cores.  A radix-16 stage is, per group of 16
 // butterflies, the product of the 16 x 16 DFT matrix with a 16 x 16 block of
-// inputs.  With complex numbers split into real and imaginary rows this is
-// two real products Yr = [Re F | -Im F] [Xr; Xi], Yi = [Im F | Re F] [Xr; Xi]
-// of a 16 x 32 matrix and a 32 x 16 block -- one v_mfma_f32_16x16x32 each.
+// inputs.  With each complex input written as two real rows (row 2r its real
+// part, row 2r + 1 its imaginary part) this is two real products Yr = Ar X,
+// Yi = Ai X of a 16 x 32 matrix and the 32 x 16 block X -- one
+// v_mfma_f32_16x16x32 each -- where Ar interleaves the columns Re F and
+// -Im F, and Ai the columns Im F and Re F.
 // FP16 / BF16 operands keep 11 / 8 significant bits, so both the DFT matrix
 // and the inputs are split into a high and a low part, x = hi + lo, and the
 // product is accumulated in FP32 as A_hi B_hi + A_hi B_lo + A_lo B_hi (the
@@ -478,9 +480,13 @@ template <typename C> __device__ __forceinline__ void transpose16_row(C *v, int 
 //
 // Operand layout of v_mfma_f32_16x16x32 (checked on the device): lane l,
 // element i holds A[l % 16][8(l/16) + i] and B[8(l/16) + i][l % 16]; the FP32
-// result D[4(l/16) + i][l % 16] is element i of lane l.  Row k of the input
-// block is the real part (k < 16) or the imaginary part (k >= 16) of input
-// r = k % 16 of butterfly n.
+// result D[4(l/16) + i][l % 16] is element i of lane l.  The input block's
+// rows and the matrix's rows are ordered so that lane row h = l/16 holds
+// inputs h, h + 4, h + 8, h + 12 of butterfly l % 16 (row 8h + 2q + c of the
+// block: component c of input h + 4q) and receives its outputs h, h + 4,
+// h + 8, h + 12 (matrix row 4h + i computes output h + 4i): four 8-byte
+// operand loads per lane, and the two rows of a 32-lane half address
+// elements one input (or one output) stride apart.
 enum { PREC_FP32 = 0, PREC_F16X2 = 1, PREC_BF16X2 = 2 };
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
@@ -539,14 +545,17 @@ template <int PREC> __global__ void dft_operand_table(typename MfmaOps<PREC>::V 
     const int lane = threadIdx.x & 63;
     float ar[8], ai[8];
     const int m = lane & 15;
+    // row m of the operand computes output o = m/4 + 4 (m mod 4); column
+    // 8 (l/16) + i multiplies component i mod 2 of input l/16 + 4 (i/2)
+    const int o = (m >> 2) + 4 * (m & 3);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const int k = 8 * (lane >> 4) + i, r = k & 15, e = (m * r) & 15;
+        const int r = (lane >> 4) + 4 * (i >> 1), e = (o * r) & 15;
         double sn, cs;
         sincospi(double(e) / 8.0, &sn, &cs); // angle 2*pi*e/16
-        // F[m][r] = cos - i sin;  Yr = sum cos Xr + sin Xi;  Yi = sum -sin Xr + cos Xi
-        ar[i] = float(k < 16 ? cs : sn);
-        ai[i] = float(k < 16 ? -sn : cs);
+        // F[o][r] = cos - i sin;  Yr = sum cos Xr + sin Xi;  Yi = sum -sin Xr + cos Xi
+        ar[i] = float((i & 1) == 0 ? cs : sn);
+        ai[i] = float((i & 1) == 0 ? -sn : cs);
     }
     typename MfmaOps<PREC>::V rh, rl, ih, il;
     split_hilo<PREC>(ar, rh, rl);
@@ -557,85 +566,184 @@ template <int PREC> __global__ void dft_operand_table(typename MfmaOps<PREC>::V 
     out[4 * lane + 3] = il;
 }
 
+// 4 x 4 transpose of 8-word blocks across the four 16-lane rows of a
+// wavefront: lane (n, h) (row h = lane / 16) holds blocks x[0..3]; afterwards
+// x[g] holds what was block h of lane (n, g).  Step one swaps blocks between
+// the two 32-lane halves (v_permlane32_swap: rows 2, 3 of the first operand
+// with rows 0, 1 of the second), step two between the rows of each half
+// (v_permlane16_swap: odd rows of the first operand with even rows of the
+// second).  The transpose is its own inverse.
+__device__ __forceinline__ void row_transpose4(float (&x)[4][8]) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int f = 0; f < 8; ++f) {
+            const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[d][f]), __float_as_uint(x[2 + d][f]),
+                                                            false, false);
+            x[d][f] = __uint_as_float(r[0]);
+            x[2 + d][f] = __uint_as_float(r[1]);
+        }
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int f = 0; f < 8; ++f) {
+            const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x[2 * c][f]),
+                                                            __float_as_uint(x[2 * c + 1][f]), false, false);
+            x[2 * c][f] = __uint_as_float(r[0]);
+            x[2 * c + 1][f] = __uint_as_float(r[1]);
+        }
+}
+
+// One group of 16 radix-16 butterflies on the matrix cores: x is this lane's
+// share of the input block (inputs h, h + 4, h + 8, h + 12 of butterfly
+// l % 16, h = l/16, real and imaginary parts interleaved); on return yr[i],
+// yi[i] hold output h + 4i of that butterfly, to be multiplied by
+// `unscale`.
+template <int PREC>
+__device__ __forceinline__ void mfma_butterflies(float (&x)[8], const DftOperands<PREC> &F, f32x4 &yr, f32x4 &yi,
+                                                 float &unscale) {
+    using Ops = MfmaOps<PREC>;
+    float scale = 1.f;
+    unscale = 1.f;
+    if constexpr (Ops::SCALE) {
+        float mx = 0.f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) mx = fmaxf(mx, fabsf(x[i]));
+        // the butterfly's four lanes (n, n + 16, n + 32, n + 48): a swap of a
+        // register with itself leaves both halves' values side by side
+        const auto m32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(mx), __float_as_uint(mx), false, false);
+        mx = fmaxf(__uint_as_float(m32[0]), __uint_as_float(m32[1]));
+        const auto m16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(mx), __float_as_uint(mx), false, false);
+        mx = fmaxf(__uint_as_float(m16[0]), __uint_as_float(m16[1]));
+        if (mx > 0.f) {
+            const int e = __builtin_amdgcn_frexp_expf(mx); // mx in [2^(e-1), 2^e)
+            scale = __builtin_amdgcn_ldexpf(1.f, 15 - e);
+            unscale = __builtin_amdgcn_ldexpf(1.f, e - 15);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i] *= scale;
+    }
+    typename Ops::V bh, bl;
+    split_hilo<PREC>(x, bh, bl);
+    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    yr = Ops::mma(F.rh, bh, z);
+    yr = Ops::mma(F.rh, bl, yr);
+    yr = Ops::mma(F.rl, bh, yr);
+    yi = Ops::mma(F.ih, bh, z);
+    yi = Ops::mma(F.ih, bl, yi);
+    yi = Ops::mma(F.il, bh, yi);
+}
+
 // The whole radix-16 stage schedule of a tile on the matrix cores.  N is a
 // power of 16 (every stage radix 16); each wave owns 64 butterflies per stage
-// (four groups of 16), so T * N/16 must be a multiple of 64.
+// (four groups of 16).
 //   v      on entry the thread's 16 inputs of stage 0 (slot r = element
 //          j + r*N/16 of line c), on exit its 16 outputs in the same layout
-//   tile   the LDS tile (complex elements, line pitch `pitch`)
-//   twl    the stage twiddle tables (as for run_stages)
-// Stage s writes output k of butterfly b to (b/NS)*NS*16 + b%NS + k*NS and
-// applies there the twiddle the next stage would apply to that element.
-template <int PREC, int N>
-__device__ __forceinline__ void mfma_stages(float2 *v, float2 *tile, int pitch, const float2 *twl, int c, int j,
-                                            int tid, const DftOperands<PREC> &F) {
-    using Ops = MfmaOps<PREC>;
+//   tile   the LDS tile (complex elements, line pitch `pitch`); free on entry
+//   twl    the stage twiddle tables (as for run_stages), written by the
+//          caller and published by the first barrier here (as the caller's
+//          weight table is) when there are two stages or more
+// Thread t's (c, j) is (t mod T, t / T) when LINES_FIRST, else (t / (N/16),
+// t mod N/16).  In the first and the last stage group g of a wave takes the
+// butterflies of the wave's lanes 16g .. 16g + 15, so the operands of the
+// first stage and the results of the last move between the thread layout and
+// the matrix-core layout by a transpose across the wave's rows
+// (row_transpose4), not through LDS; the stages in between take the tile's
+// butterflies line by line.  Stage s writes output k of butterfly b to
+// (b/NS)*NS*16 + b%NS + k*NS and applies there the twiddle the next stage
+// would apply to that element.
+template <int PREC, int N, bool LINES_FIRST>
+__device__ __forceinline__ void mfma_stages(float2 *v, float2 *tile, int pitch, const float2 *twl, int log2T, int tid,
+                                            const DftOperands<PREC> &F) {
     constexpr int TPL = N / 16, NST = sched_nstages(N, 16);
     static_assert(N >= 16 && ilog2c(N) % 4 == 0, "all stages radix 16");
-    const int lane = tid & 63, wave = tid >> 6;
-    const int rb = 8 * ((lane >> 4) & 1), comp = lane >> 5, kb = 4 * (lane >> 4);
+    const int lane = tid & 63, wave = tid >> 6, hh = lane >> 4;
+    // line and butterfly of group g in stage s
+    auto butterfly = [&](int s, int g, int &cc, int &b) {
+        const int t = 64 * wave + 16 * g + (lane & 15);
+        if (s == 0 || s == NST - 1) {
+            if constexpr (LINES_FIRST) {
+                cc = t & ((1 << log2T) - 1);
+                b = t >> log2T;
+            } else {
+                cc = t / TPL;
+                b = t % TPL;
+            }
+        } else {
+            cc = t / TPL;
+            b = t % TPL;
+        }
+    };
+    float x[4][8];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) tile[c * pitch + lpad<N>(j + r * TPL)] = v[r];
-    __syncthreads();
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            x[h][2 * q] = v[h + 4 * q].x;
+            x[h][2 * q + 1] = v[h + 4 * q].y;
+        }
+    row_transpose4(x);
 #pragma unroll
     for (int s = 0; s < NST; ++s) {
         const int NS = 1 << (4 * s);
-        float x[4][8];
+        if (s > 0) {
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const int bf = 64 * wave + 16 * g + (lane & 15), cc = bf / TPL, b = bf % TPL;
-            const float *ln = reinterpret_cast<const float *>(tile + cc * pitch);
+            for (int g = 0; g < 4; ++g) {
+                int cc, b;
+                butterfly(s, g, cc, b);
+                const float2 *ln = tile + cc * pitch;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) x[g][i] = ln[2 * lpad<N>(b + (rb + i) * TPL) + comp];
-        }
-        __syncthreads(); // every read of this stage precedes its writes
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            float scale = 1.f, unscale = 1.f;
-            if constexpr (Ops::SCALE) {
-                float mx = 0.f;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) mx = fmaxf(mx, fabsf(x[g][i]));
-                mx = fmaxf(mx, __shfl_xor(mx, 16));
-                mx = fmaxf(mx, __shfl_xor(mx, 32));
-                if (mx > 0.f) {
-                    const int e = __builtin_amdgcn_frexp_expf(mx); // mx in [2^(e-1), 2^e)
-                    scale = __builtin_amdgcn_ldexpf(1.f, 15 - e);
-                    unscale = __builtin_amdgcn_ldexpf(1.f, e - 15);
+                for (int q = 0; q < 4; ++q) {
+                    const float2 e = ln[lpad<N>(b + (hh + 4 * q) * TPL)];
+                    x[g][2 * q] = e.x;
+                    x[g][2 * q + 1] = e.y;
                 }
-#pragma unroll
-                for (int i = 0; i < 8; ++i) x[g][i] *= scale;
             }
-            typename Ops::V bh, bl;
-            split_hilo<PREC>(x[g], bh, bl);
-            const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-            f32x4 yr = Ops::mma(F.rh, bh, z);
-            yr = Ops::mma(F.rh, bl, yr);
-            yr = Ops::mma(F.rl, bh, yr);
-            f32x4 yi = Ops::mma(F.ih, bh, z);
-            yi = Ops::mma(F.ih, bl, yi);
-            yi = Ops::mma(F.il, bh, yi);
-            const int bf = 64 * wave + 16 * g + (lane & 15), cc = bf / TPL, b = bf % TPL;
+        }
+        // The four groups' products, results in place of their operands
+        // (still scaled when a twiddle follows: the twiddle takes `unscale`).
+        float unscale[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            f32x4 yr, yi;
+            mfma_butterflies<PREC>(x[g], F, yr, yi, unscale[g]);
+            const float u = s + 1 < NST ? 1.f : unscale[g];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int k = kb + i, p = (b / NS) * NS * 16 + (b % NS) + k * NS;
-                float2 o = mk<float2>(yr[i] * unscale, yi[i] * unscale);
-                if (s + 1 < NST) {
+                x[g][2 * i] = yr[i] * u;
+                x[g][2 * i + 1] = yi[i] * u;
+            }
+        }
+        if (s + 1 < NST) {
+            // Stage 0: the caller's LDS tables (twl, the weight table) are
+            // published; later stages: every read of this stage precedes its
+            // writes.
+            __syncthreads();
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                int cc, b;
+                butterfly(s, g, cc, b);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = hh + 4 * i, p = (b / NS) * NS * 16 + (b % NS) + k * NS;
                     // next stage's twiddle of element p: input r2 = p / TPL of
                     // butterfly b2 = p % TPL, exponent r2 * (b2 mod 16^(s+1))
                     const int NS2 = NS * 16, r2 = p / TPL, k2 = (p % TPL) & (NS2 - 1);
                     const int off = tw_stage_off(N, 16, s + 1);
                     float2 w = twl[off + (k2 & 15) * 17 + r2];
                     if (NS2 > 16) w = cmul(w, twl[off + (16 + (k2 >> 4)) * 17 + r2]);
-                    o = cmulc(o, w);
+                    w = mk<float2>(w.x * unscale[g], w.y * unscale[g]);
+                    tile[cc * pitch + lpad<N>(p)] = cmulc(mk<float2>(x[g][2 * i], x[g][2 * i + 1]), w);
                 }
-                tile[cc * pitch + lpad<N>(p)] = o;
             }
+            __syncthreads(); // this stage's writes precede the next stage's reads
         }
-        __syncthreads();
     }
+    row_transpose4(x);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = tile[c * pitch + lpad<N>(j + r * TPL)];
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[h + 4 * q] = mk<float2>(x[h][2 * q], x[h][2 * q + 1]);
 }
 
 } // namespace liftfft

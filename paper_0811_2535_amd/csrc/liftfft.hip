@@ -479,7 +479,7 @@ template <typename Real, int N, int RMAX, int KIND, int EMAX, bool SPLIT, int PR
         } else if constexpr (PREC == PREC_FP32) {
             run_stages<C, N, RMAX, E, SPLIT>(v, line, twl, j);
         } else {
-            mfma_stages<PREC, N>(v, tile, a.pitch, twl, c, j, tid, F);
+            mfma_stages<PREC, N, KIND != K_SINGLE>(v, tile, a.pitch, twl, log2T, tid, F);
         }
 
         if (!active) return;
