@@ -514,12 +514,33 @@ template <> struct MfmaOps<PREC_BF16X2> {
 // x = hi + lo in the operand type (lo rounds the remainder once more).
 template <int PREC>
 __device__ __forceinline__ void split_hilo(const float *x, typename MfmaOps<PREC>::V &hi, typename MfmaOps<PREC>::V &lo) {
-    using S = typename MfmaOps<PREC>::S;
+    using V = typename MfmaOps<PREC>::V;
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    if constexpr (PREC == PREC_BF16X2) {
+        // A BF16 value is the upper half of the FP32 value it stands for, so
+        // the hi parts come back to FP32 by a shift or a mask of the packed
+        // pair, not by converting each one again.
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const S h = S(x[i]);
-        hi[i] = h;
-        lo[i] = S(x[i] - float(h));
+        for (int i = 0; i < 8; i += 2) {
+            const bf16x2 h = __builtin_convertvector((f32x2){x[i], x[i + 1]}, bf16x2);
+            const uint32_t u = __builtin_bit_cast(uint32_t, h);
+            const bf16x2 l = __builtin_convertvector(
+                (f32x2){x[i] - __uint_as_float(u << 16), x[i + 1] - __uint_as_float(u & 0xffff0000u)}, bf16x2);
+            hi[i] = h[0];
+            hi[i + 1] = h[1];
+            lo[i] = l[0];
+            lo[i + 1] = l[1];
+        }
+    } else {
+        // whole-vector conversions: two values per packed conversion, and the
+        // remainders formed by mixed-precision FMAs from the FP16 hi parts
+        typedef float f32x8 __attribute__((ext_vector_type(8)));
+        f32x8 xv;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) xv[i] = x[i];
+        hi = __builtin_convertvector(xv, V);
+        lo = __builtin_convertvector(xv - __builtin_convertvector(hi, f32x8), V);
     }
 }
 
