@@ -135,6 +135,16 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out);
  *                     options FFT_E_ARG.  Inputs not 16-byte aligned run
  *                     the plain pass 1.  A measured alternative: slower
  *                     than the default pass 1 at n = 2^24.
+ *                     FFT_OPT_DEBUG_CANARY (a debug mode, any plan of
+ *                     fft_plan_create_ex): every execute first fills the
+ *                     scratch array, and `out` wherever a pass reads
+ *                     neither it nor the input afterwards, with quiet NaNs
+ *                     on the execute stream (before pass 1, and again
+ *                     before the pass that writes `out` last), so that an
+ *                     element a pass reads before any pass has written it
+ *                     reaches the output as a NaN.  The transform's
+ *                     result is unchanged, bit for bit; the fills cost
+ *                     time, and the per-pass timing includes them.
  *                     FFT_OPT_THREE_LEVEL takes no two-level options
  *                     (log2_p, lines_per_block2, values_per_thread2,
  *                     scratch_width: FFT_E_ARG); lines_per_block then sets
@@ -177,7 +187,8 @@ enum {
     FFT_OPT_TWO_LEVEL = 128,
     FFT_OPT_THREE_LEVEL = 256,
     FFT_OPT_SHUFFLE_EXCHANGE = 512,
-    FFT_OPT_LDS_PREFETCH = 2048
+    FFT_OPT_LDS_PREFETCH = 2048,
+    FFT_OPT_DEBUG_CANARY = 4096
 };
 typedef struct fft_plan_opts {
     int32_t log2_p;
@@ -413,7 +424,16 @@ int fft_plan_read_timing(fft_plan *plan, double ms_out[3], int64_t launches_out[
  * problem size on one machine (Section 8 of the paper); the outcome is
  * remembered per (n, batch, dtype, device) for the life of the process, and
  * a later call with the same shape creates the remembered configuration
- * without timing.  Synchronous; the device is otherwise idle-assumed (other
+ * without timing.  If the environment variable LIFTFFT_TUNE_CACHE names a
+ * file, outcomes are also kept there across processes: one JSON object per
+ * line with the device's architecture name (hipDeviceProp_t::gcnArchName),
+ * n, batch, dtype, the eight fields of fft_plan_opts, ms, ms_default,
+ * candidates and rejected; a call whose shape is not remembered in the
+ * process looks the file up (the last matching line wins; a configuration
+ * this build cannot create is tuned again) and returns the stored result
+ * without timing, and every new outcome is appended as one line (a file
+ * that cannot be read or written is ignored).  Synchronous; the device is
+ * otherwise idle-assumed (other
  * work on it skews the timings, not the results).  Errors as
  * fft_plan_create, plus FFT_E_ARG for max_candidates < 0.
  */

@@ -56,6 +56,7 @@ FFT_OPT_THREE_LEVEL = 256
 FFT_OPT_SHUFFLE_EXCHANGE = 512
 FFT_OPT_AUTOTUNE = 1024
 FFT_OPT_LDS_PREFETCH = 2048
+FFT_OPT_DEBUG_CANARY = 4096
 
 
 class PlanOpts(ctypes.Structure):

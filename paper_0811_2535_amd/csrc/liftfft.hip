@@ -35,6 +35,7 @@
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -45,6 +46,7 @@
 #include <mutex>
 #include <type_traits>
 #include <new>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -953,6 +955,12 @@ __global__ void twiddle_table_kernel(typename Cx<Real>::T *out, int64_t count, i
     out[i] = w;
 }
 
+// Debug mode: fill `words` 32-bit words with a quiet NaN (grid-stride).
+__global__ void canary_fill_kernel(uint32_t *__restrict__ p, int64_t words) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < words; i += stride) p[i] = 0x7fc00000u;
+}
+
 // Tuner helpers.  A deterministic input pattern in [-1, 1) (an integer
 // hash of the index), and per-block maxima of |a - b| and |b| for comparing
 // two outputs (finished on the host).
@@ -1217,6 +1225,7 @@ struct fft_plan {
     void *meta = nullptr; // device: classes and transform offsets
     size_t meta_bytes = 0;
     bool use_graph = false;
+    bool canary = false; // FFT_OPT_DEBUG_CANARY
     // Execute-time bookkeeping (mutable: fft_execute takes a const plan, whose
     // transform it only reads): the graph cache of uneven batches and the
     // timing event ring.
@@ -1645,7 +1654,7 @@ int shape_plan(fft_plan *p, int64_t n, int64_t batch, int dtype, const fft_plan_
     constexpr int32_t known_flags = FFT_OPT_NO_XCD_REMAP | FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE |
                                     FFT_OPT_PERSISTENT | FFT_OPT_ONE_TILE | FFT_OPT_DENSE |
                                     FFT_OPT_TWO_LEVEL | FFT_OPT_THREE_LEVEL | FFT_OPT_SHUFFLE_EXCHANGE |
-                                    FFT_OPT_LDS_PREFETCH;
+                                    FFT_OPT_LDS_PREFETCH | FFT_OPT_DEBUG_CANARY;
     // the staged pass 1 is a two-level variant of its own
     if ((o.flags & FFT_OPT_LDS_PREFETCH) &&
         (!(o.flags & FFT_OPT_TWO_LEVEL) || (o.flags & (FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE |
@@ -1687,6 +1696,7 @@ int shape_plan(fft_plan *p, int64_t n, int64_t batch, int dtype, const fft_plan_
     p->log2n = t;
     p->radix = radix;
     p->esize = esize;
+    p->canary = (o.flags & FFT_OPT_DEBUG_CANARY) != 0;
     if (hipGetDevice(&p->device) != hipSuccess) {
         (void)hipGetLastError();
         return FFT_E_HIP;
@@ -2345,8 +2355,19 @@ namespace {
 
 // Enqueue every launch of plan p on stream st (arguments already checked,
 // p's device current).
+// Debug mode: quiet NaNs over `bytes` bytes at `dst` (stream order).
+int canary_fill(void *dst, size_t bytes, hipStream_t st) {
+    const int64_t words = int64_t(bytes / 4);
+    if (words <= 0) return FFT_OK;
+    const int64_t blocks = (words + 255) / 256 < 4096 ? (words + 255) / 256 : 4096;
+    hipLaunchKernelGGL(canary_fill_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, static_cast<uint32_t *>(dst),
+                       words);
+    return hipGetLastError() == hipSuccess ? FFT_OK : FFT_E_HIP;
+}
+
 int launch_plan(const fft_plan *p, const void *in, void *out, int sign, hipStream_t st) {
     const bool inv = sign > 0;
+    const size_t out_bytes = size_t(p->total) * p->esize;
     PassArgs a;
     memset(&a, 0, sizeof(a));
     a.n = p->n;
@@ -2376,6 +2397,7 @@ int launch_plan(const fft_plan *p, const void *in, void *out, int sign, hipStrea
             if (rc == FFT_OK && ev) rc = hipEventRecord(ev[phase + 1], st) == hipSuccess ? FFT_OK : FFT_E_HIP;
         }
     } else if (p->passes == 1) {
+        if (rc == FFT_OK && p->canary && out != in) rc = canary_fill(out, out_bytes, st);
         a.in = in;
         a.out = out;
         a.tw = p->tw1;
@@ -2400,7 +2422,14 @@ int launch_plan(const fft_plan *p, const void *in, void *out, int sign, hipStrea
         const int32_t outs[3][3] = {{0, l1, l1 + l2}, {0, l1 + l2, l1}, {0, l3, l2 + l3}};
         a.tw_hi = p->tw_hi;
         a.tw_lo = p->tw_lo;
+        if (rc == FFT_OK && p->canary) {
+            rc = canary_fill(p->scratch, p->scratch_bytes, st);
+            if (rc == FFT_OK && out != in) rc = canary_fill(out, out_bytes, st);
+        }
         for (int k = 0; k < 3 && rc == FFT_OK; ++k) {
+            // pass C rewrites `out`, which pass B has finished reading
+            if (k == 2 && p->canary) rc = canary_fill(out, out_bytes, st);
+            if (rc != FFT_OK) break;
             a.in = src[k];
             a.out = dst[k];
             a.tw = tw[k];
@@ -2427,6 +2456,7 @@ int launch_plan(const fft_plan *p, const void *in, void *out, int sign, hipStrea
         // the plain pass-1 kernel.
         const Launch &K1 =
             p->k1.var.lds_prefetch && (reinterpret_cast<uintptr_t>(in) & 15) ? p->k1_plain : p->k1;
+        if (rc == FFT_OK && p->canary) rc = canary_fill(p->scratch, p->scratch_bytes, st);
         a.in = in;
         a.out = p->scratch;
         a.tw = p->tw1;
@@ -2442,6 +2472,8 @@ int launch_plan(const fft_plan *p, const void *in, void *out, int sign, hipStrea
         a.xcd_remap = K1.remap;
         if (rc == FFT_OK) rc = launch(p, K1, a, st);
         if (rc == FFT_OK && ev) rc = hipEventRecord(ev[1], st) == hipSuccess ? FFT_OK : FFT_E_HIP;
+        // pass 1 has read the input: `out` (possibly the input) is free
+        if (rc == FFT_OK && p->canary) rc = canary_fill(out, out_bytes, st);
         a.in = p->scratch;
         a.out = out;
         a.tw = p->tw2;
@@ -2710,6 +2742,117 @@ struct TuneKey {
 std::mutex tune_mutex;
 std::map<TuneKey, fft_tune_result> tune_cache;
 
+// Tuning outcomes kept across processes when the environment variable
+// LIFTFFT_TUNE_CACHE names a file: one JSON object per line, keyed by the
+// device's architecture name, n, batch and dtype (the last line of a key
+// wins), holding the chosen options and the tuner's timings.
+std::string device_arch(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        (void)hipGetLastError();
+        return std::string();
+    }
+    return std::string(prop.gcnArchName);
+}
+
+// The value after "key": on one line of the cache file.
+const char *json_value(const char *line, const char *key) {
+    char pat[64];
+    snprintf(pat, sizeof pat, "\"%s\":", key);
+    const char *v = strstr(line, pat);
+    if (!v) return nullptr;
+    v += strlen(pat);
+    while (*v == ' ') ++v;
+    return v;
+}
+bool json_int(const char *line, const char *key, int64_t &out) {
+    const char *v = json_value(line, key);
+    if (!v) return false;
+    char *end = nullptr;
+    const long long x = strtoll(v, &end, 10);
+    if (end == v) return false;
+    out = x;
+    return true;
+}
+bool json_double(const char *line, const char *key, double &out) {
+    const char *v = json_value(line, key);
+    if (!v) return false;
+    char *end = nullptr;
+    const double x = strtod(v, &end);
+    if (end == v) return false;
+    out = x;
+    return true;
+}
+bool json_string(const char *line, const char *key, std::string &out) {
+    const char *v = json_value(line, key);
+    if (!v || *v != '"') return false;
+    const char *e = strchr(v + 1, '"');
+    if (!e) return false;
+    out.assign(v + 1, e);
+    return true;
+}
+
+bool tune_file_lookup(const std::string &arch, int64_t n, int64_t batch, int dtype, fft_tune_result &out) {
+    const char *path = getenv("LIFTFFT_TUNE_CACHE");
+    if (!path || !*path || arch.empty()) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[2048];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        std::string a;
+        int64_t ln = 0, lb = 0, ld = 0;
+        if (!json_string(line, "arch", a) || a != arch || !json_int(line, "n", ln) || ln != n ||
+            !json_int(line, "batch", lb) || lb != batch || !json_int(line, "dtype", ld) || ld != dtype)
+            continue;
+        int64_t v[10];
+        double ms = 0, msd = 0;
+        const char *keys[10] = {"log2_p",     "radix", "lines_per_block",    "lines_per_block2", "flags",
+                                "values_per_thread", "values_per_thread2", "scratch_width", "candidates", "rejected"};
+        bool ok = json_double(line, "ms", ms) && json_double(line, "ms_default", msd);
+        for (int k = 0; k < 10 && ok; ++k) ok = json_int(line, keys[k], v[k]);
+        if (!ok) continue;
+        fft_tune_result r;
+        memset(&r, 0, sizeof r);
+        r.opts.log2_p = int32_t(v[0]);
+        r.opts.radix = int32_t(v[1]);
+        r.opts.lines_per_block = int32_t(v[2]);
+        r.opts.lines_per_block2 = int32_t(v[3]);
+        r.opts.flags = int32_t(v[4]);
+        r.opts.values_per_thread = int32_t(v[5]);
+        r.opts.values_per_thread2 = int32_t(v[6]);
+        r.opts.scratch_width = int32_t(v[7]);
+        r.candidates = int32_t(v[8]);
+        r.rejected = int32_t(v[9]);
+        r.ms = ms;
+        r.ms_default = msd;
+        out = r;
+        found = true;
+    }
+    fclose(f);
+    return found;
+}
+
+void tune_file_append(const std::string &arch, int64_t n, int64_t batch, int dtype, const fft_tune_result &r) {
+    const char *path = getenv("LIFTFFT_TUNE_CACHE");
+    if (!path || !*path || arch.empty()) return;
+    char line[1024];
+    const int len = snprintf(line, sizeof line,
+                             "{\"arch\": \"%s\", \"n\": %lld, \"batch\": %lld, \"dtype\": %d, \"log2_p\": %d, "
+                             "\"radix\": %d, \"lines_per_block\": %d, \"lines_per_block2\": %d, \"flags\": %d, "
+                             "\"values_per_thread\": %d, \"values_per_thread2\": %d, \"scratch_width\": %d, "
+                             "\"ms\": %.6g, \"ms_default\": %.6g, \"candidates\": %d, \"rejected\": %d}\n",
+                             arch.c_str(), (long long)n, (long long)batch, dtype, r.opts.log2_p, r.opts.radix,
+                             r.opts.lines_per_block, r.opts.lines_per_block2, r.opts.flags, r.opts.values_per_thread,
+                             r.opts.values_per_thread2, r.opts.scratch_width, r.ms, r.ms_default, r.candidates,
+                             r.rejected);
+    if (len <= 0 || len >= int(sizeof line)) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fputs(line, f); // one write of a whole line: concurrent appends do not interleave
+    fclose(f);
+}
+
 // Candidate configurations, most promising first: the default; the other
 // splits n = p*q near the square one and the single/two-pass threshold;
 // radix 2; then, for the default split, the kernel variants and tile widths.
@@ -2851,9 +2994,13 @@ int fft_plan_create_tuned(int64_t n, int64_t batch, int dtype, int32_t max_candi
     int rc = fft_plan_create(n, batch, dtype, &best);
     if (rc != FFT_OK) return rc;
     const TuneKey key{n, batch, dtype, best->device};
+    const std::string arch = device_arch(best->device);
     {
         std::lock_guard<std::mutex> g(tune_mutex);
         auto it = tune_cache.find(key);
+        fft_tune_result stored;
+        if (it == tune_cache.end() && tune_file_lookup(arch, n, batch, dtype, stored))
+            it = tune_cache.emplace(key, stored).first;
         if (it != tune_cache.end()) {
             fft_plan *p = nullptr;
             rc = fft_plan_create_ex(n, batch, dtype, &it->second.opts, &p);
@@ -2863,6 +3010,7 @@ int fft_plan_create_tuned(int64_t n, int64_t batch, int dtype, int32_t max_candi
                 *plan_out = p;
                 return FFT_OK;
             }
+            tune_cache.erase(it); // a stored configuration this build cannot create: tune again
         }
     }
     TuneBench b;
@@ -2937,6 +3085,7 @@ int fft_plan_create_tuned(int64_t n, int64_t batch, int dtype, int32_t max_candi
     {
         std::lock_guard<std::mutex> g(tune_mutex);
         tune_cache[key] = res;
+        tune_file_append(arch, n, batch, dtype, res);
     }
     if (result) *result = res;
     *plan_out = best;

@@ -130,7 +130,7 @@ def test_create_many_validation():
     big = arr(*([1 << 24] * 32))
     assert L.fft_plan_create_many(big, 32, 0, 0, ctypes.byref(h)) == -8
     # flags: 0 or FFT_OPT_GRAPH; every other bit is refused before any device work
-    for flags in (1, 2, 4, 16, 32, 128, 256, 512, 1 << 31, 0xFFFFFFFF, 64 | 1, 8 | 1024):
+    for flags in (1, 2, 4, 16, 32, 128, 256, 512, 2048, 4096, 1 << 31, 0xFFFFFFFF, 64 | 1, 8 | 1024):
         assert L.fft_plan_create_many(arr(8, 16), 2, 0, flags, ctypes.byref(h)) == -9, flags
         assert h.value is None
 

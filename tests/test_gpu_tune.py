@@ -42,3 +42,60 @@ def test_tuned_plan(torch, t, batch, dtype, tol, cands):
     plan2, res2 = lf.Plan.tuned(n, batch, tdt, max_candidates=cands)
     assert res2 == res
     plan2.destroy()
+
+
+CACHE_CHILD = r"""
+import json, os, sys
+sys.path.insert(0, sys.argv[1])
+import torch
+import paper_0811_2535_amd as lf
+plan, res = lf.Plan.tuned(int(sys.argv[2]), int(sys.argv[3]), torch.complex64, max_candidates=4)
+info = plan.info()
+plan.destroy()
+print(json.dumps({"res": res, "info": {k: info[k] for k in ("passes", "log2_p")}}))
+"""
+
+
+def test_tuner_cache_file(torch, tmp_path):
+    """With LIFTFFT_TUNE_CACHE set, a tuning outcome is appended to the file
+    as one JSON line keyed by (arch, n, batch, dtype), and a fresh process
+    asking for the same shape returns the stored configuration and timings
+    without tuning (the last matching line wins)."""
+    import json
+    import os
+    import subprocess
+    import sys
+
+    import paper_0811_2535_amd as lf
+    path = tmp_path / "tune.jsonl"
+    n, batch = 1 << 14, 5  # a shape no other test tunes in this process
+    os.environ["LIFTFFT_TUNE_CACHE"] = str(path)
+    try:
+        announce("tune cache: tune n=2^14 batch=5 into %s" % path)
+        plan, res = lf.Plan.tuned(n, batch, torch.complex64, max_candidates=4)
+        plan.destroy()
+    finally:
+        del os.environ["LIFTFFT_TUNE_CACHE"]
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1, lines
+    rec = json.loads(lines[0])
+    assert rec["arch"].startswith("gfx950"), rec
+    assert (rec["n"], rec["batch"], rec["dtype"]) == (n, batch, 0), rec
+    assert rec["candidates"] == res["candidates"] and abs(rec["ms"] - res["ms"]) <= 1e-6 * max(1.0, res["ms"])
+    # a later line for the same key, naming a configuration the tuner would
+    # not report by itself: the two-level lift 64 x 256
+    forged = dict(rec, log2_p=6, radix=0, lines_per_block=0, lines_per_block2=0, flags=128, values_per_thread=0,
+                  values_per_thread2=0, scratch_width=0, ms=123.0, ms_default=456.0, candidates=99)
+    with open(path, "a") as f:
+        f.write(json.dumps(forged) + "\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, LIFTFFT_TUNE_CACHE=str(path))
+    announce("tune cache: fresh process reads n=2^14 batch=5 from the file")
+    out = subprocess.run([sys.executable, "-c", CACHE_CHILD, root, str(n), str(batch)], env=env,
+                         capture_output=True, text=True, timeout=180)
+    assert out.returncode == 0, out.stderr[-2000:]
+    got = json.loads(out.stdout.strip().splitlines()[-1])
+    assert got["res"]["ms"] == 123.0 and got["res"]["candidates"] == 99, got
+    assert got["res"]["opts"]["log2_p"] == 6 and got["res"]["opts"]["flags"] == 128, got
+    assert got["info"]["passes"] == 2 and got["info"]["log2_p"] == 6, got
+    assert len(path.read_text().splitlines()) == 2  # a hit appends nothing
