@@ -68,10 +68,32 @@ def test_dft16_matrix_product(lf, mode):
 
 
 @pytest.mark.parametrize("mode", ["f16x2", "bf16x2"])
-@pytest.mark.parametrize("t,batch,log2_p", [(8, 8, 0), (12, 4, 0), (20, 2, 8), (24, 1, 0)])
+@pytest.mark.parametrize("t,batch", [(4, 64), (8, 8), (12, 4)])
+def test_single_pass_transform_error(lf, torch, mode, t, batch):
+    """Single-pass plans (whole lines in one workgroup, threads sweeping one
+    line first) of 16, 256 and 4096 points on the matrix cores."""
+    x = datagen.signals(1 << t, batch, np.complex64, "normal", 162 + t)
+    for sign in (-1, 1):
+        announce("precision single-pass %s n=2^%d batch=%d sign=%d" % (mode, t, batch, sign))
+        plan = lf.Plan(1 << t, batch, torch.complex64)
+        assert plan.info()["passes"] == 1
+        plan.set_precision(mode)
+        xd = to_dev(x)
+        y = torch.full_like(xd, float("nan"))
+        plan.execute(xd, y, sign)
+        torch.cuda.synchronize()
+        plan.destroy()
+        got = to_np(y)
+        ref = oracle.fft_batch(x.astype(np.complex128), sign)
+        errs = [oracle.rel_l2(got[b], ref[b]) for b in range(batch)]
+        assert max(errs) <= BOUND[mode], (mode, t, sign, errs)
+
+
+@pytest.mark.parametrize("mode", ["f16x2", "bf16x2"])
+@pytest.mark.parametrize("t,batch,log2_p", [(8, 8, 0), (12, 4, 0), (16, 4, 8), (20, 2, 8), (24, 1, 0)])
 def test_transform_error(lf, mode, t, batch, log2_p):
-    """Whole transforms: single pass at 256 and 4096 points, the 4096 x 256
-    lift of 2^20 (every stage radix 16), and 2^24 (4096 x 4096)."""
+    """Whole two-level transforms at 2^8 and 2^12 (the default splits),
+    2^16 (256 x 256), 2^20 (4096 x 256) and 2^24 (4096 x 4096)."""
     x = datagen.signals(1 << t, batch, np.complex64, "normal", 62 + t)
     for sign in (-1, 1):
         announce("precision %s n=2^%d batch=%d sign=%d" % (mode, t, batch, sign))
