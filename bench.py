@@ -416,33 +416,16 @@ def measure_ragged(torch, lf, datagen, reps: int = 10) -> dict:
     xs = [torch.from_numpy(x_np).to(dev) for _ in range(sets)]
     ys = [torch.empty_like(xs[0]) for _ in range(sets)]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ms_mode = {}
     # class plans on forked streams (the default), the persistent-launch
     # form, each launched directly and replayed as a captured graph, and the
     # class form with every class autotuned
+    forms = {}
     for key, kw in ((("classes", False), {}), (("classes", True), {"graph": True}),
                     (("persistent", False), {"persistent": True}),
                     (("persistent", True), {"persistent": True, "graph": True}),
                     (("tuned", False), {"autotune": True})):
-        plan = lf.Plan.uneven(lengths, torch.complex64, **kw)
-        for i in range(sets):
-            plan.execute(xs[i], ys[i], -1)
-        torch.cuda.synchronize()
-        e0.record()
-        for i in range(reps):
-            plan.execute(xs[i % sets], ys[i % sets], -1)
-        e1.record()
-        torch.cuda.synchronize()
-        ms_mode[key] = e0.elapsed_time(e1) / reps
-        if key == ("classes", False):
-            info = plan.info()
-        plan.destroy()
-    ms_direct, ms_graph = ms_mode[("classes", False)], ms_mode[("classes", True)]
-    plan = lf.Plan.uneven(lengths, torch.complex64)
-    plan.execute(xs[0], ys[0], -1)
-    torch.cuda.synchronize()
-    plan.destroy()
-    keep = (x_np, ys[0].cpu().numpy(), lengths)
+        forms[key] = lf.Plan.uneven(lengths, torch.complex64, **kw)
+    info = forms[("classes", False)].info()
 
     # (a) per-class batched plans on contiguous class buffers.
     offs = np.concatenate([[0], np.cumsum(lengths)[:-1]])
@@ -455,19 +438,41 @@ def measure_ragged(torch, lf, datagen, reps: int = 10) -> dict:
         xb = [torch.from_numpy(block).to(dev) for _ in range(sets)]
         yb = [torch.empty_like(xb[0]) for _ in range(sets)]
         cls_bufs.append((lf.Plan(ln, len(idx), torch.complex64), xb, yb))
-    for pl, xb, yb in cls_bufs:
-        pl.execute(xb[0], yb[0], -1)
+
+    def run_form(key, i):
+        if key == "per_class":
+            for pl, xb, yb in cls_bufs:
+                pl.execute(xb[i % sets], yb[i % sets], -1)
+        else:
+            forms[key].execute(xs[i % sets], ys[i % sets], -1)
+
+    # Every form warmed up, then timed in turn over three rounds (median).
+    keys = list(forms) + ["per_class"]
+    for key in keys:
+        for i in range(sets):
+            run_form(key, i)
     torch.cuda.synchronize()
-    e0.record()
-    for i in range(reps):
-        for pl, xb, yb in cls_bufs:
-            pl.execute(xb[i % sets], yb[i % sets], -1)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_classes = e0.elapsed_time(e1) / reps
+    times = {k: [] for k in keys}
+    for _ in range(3):
+        for key in keys:
+            e0.record()
+            for i in range(reps):
+                run_form(key, i)
+            e1.record()
+            torch.cuda.synchronize()
+            times[key].append(e0.elapsed_time(e1) / reps)
+    ms_mode = {k: sorted(v)[len(v) // 2] for k, v in times.items()}
+    for plan in forms.values():
+        plan.destroy()
     for pl, _, _ in cls_bufs:
         pl.destroy()
     del cls_bufs
+    ms_direct, ms_graph, ms_classes = ms_mode[("classes", False)], ms_mode[("classes", True)], ms_mode["per_class"]
+    plan = lf.Plan.uneven(lengths, torch.complex64)
+    plan.execute(xs[0], ys[0], -1)
+    torch.cuda.synchronize()
+    plan.destroy()
+    keep = (x_np, ys[0].cpu().numpy(), lengths)
 
     # (b) one launch per transform (views into the packed buffers).
     plans = {ln: lf.Plan(ln, 1, torch.complex64) for ln in classes}
@@ -497,7 +502,7 @@ def measure_ragged(torch, lf, datagen, reps: int = 10) -> dict:
             "speedup_vs_per_transform": round(ms_each / ms_direct, 3)}, keep
 
 
-def measure_precision(torch, lf, datagen, reps: int = 5):
+def measure_precision(torch, lf, datagen, reps: int = 5, rounds: int = 3):
     """Precision forms on 256 transforms of 2^20 complex64 (N(0,1), seed 4),
     lifted 4096 x 256 so every stage is radix 16: FP32 stages on the vector
     units against radix-16 stages on the matrix cores with FP16 / BF16 pairs.
@@ -516,23 +521,41 @@ def measure_precision(torch, lf, datagen, reps: int = 5):
     plan = lf.Plan(n, batch, torch.complex64, log2_p=8)
     out = {"workload": "256 x 2^20 c64 forward, lift 4096 x 256 (all stages radix 16)"}
     flops = 5.0 * n * math.log2(n) * batch
-    for mode in ("fp32", "f16x2", "bf16x2"):
+    modes = ("fp32", "f16x2", "bf16x2")
+    # Steady state for every form: each is warmed up, then the forms are timed
+    # in turn over `rounds` rounds and each keeps its median round (the first
+    # executes after the buffers are allocated run measurably slower, which a
+    # single round would charge to whichever form comes first).
+    for mode in modes:
+        plan.set_precision(mode)
+        for _ in range(3):
+            plan.execute(x, y, -1)
+    torch.cuda.synchronize()
+    times = {m: [] for m in modes}
+    for _ in range(rounds):
+        for mode in modes:
+            plan.set_precision(mode)
+            plan.execute(x, y, -1)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                plan.execute(x, y, -1)
+            e1.record()
+            torch.cuda.synchronize()
+            times[mode].append(e0.elapsed_time(e1) / reps)
+    for mode in modes:
         plan.set_precision(mode)
         plan.execute(x, y, -1)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            plan.execute(x, y, -1)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        ms = sorted(times[mode])[len(times[mode]) // 2]
         if y32 is None:
             y32 = y.clone()
         diff = float(torch.linalg.vector_norm((y - y32).to(torch.complex128)) /
                      torch.linalg.vector_norm(y32.to(torch.complex128)))
         firsts[mode] = y[:PRECISION_SUBSET].cpu().numpy()
-        out[mode] = {"ms": round(ms, 4), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+        out[mode] = {"ms": round(ms, 4), "ms_rounds": [round(v, 4) for v in times[mode]],
+                     "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
                      "hbm_gbps_algorithmic": round(32 * n * batch / (ms * 1e-3) / 1e9, 1),
                      "rel_l2_vs_fp32_path": float("%.3g" % diff)}
     plan.destroy()
