@@ -34,6 +34,13 @@ if ROOT not in sys.path:
 METRIC = ("GFLOP/s (5n·log2n) + HBM GB/s % peak, c64 n=2^24; fwd+bwd and batched "
           "vs plain")
 HBM_PEAK_GBS = 8000.0
+# The paper's own timing at this length, as context (another algorithm form on
+# other hardware, so no ratio is formed): Table 7.1, the sequential
+# "monolithic" FFT-UA at n = 2^24 on the SGI/Cray Origin2000 (R10000 at
+# 195 MHz), 7.550 s; GFLOP/s derived here as 5 n log2 n / t.
+PAPER_CONTEXT = {"source": "Table 7.1, FFT-UA (sequential), n = 2^24",
+                 "hardware": "SGI/Cray Origin2000, R10000 195 MHz", "seconds": 7.550,
+                 "gflops_derived": round(5.0 * (1 << 24) * 24 / 7.550 / 1e9, 3)}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c64_n2p24.txt")
 
 
@@ -1003,6 +1010,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
+        "paper_context": PAPER_CONTEXT,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
