@@ -855,6 +855,9 @@ def main() -> int:
     ap.add_argument("--summarize-trace", metavar="KERNEL_STATS_CSV",
                     help="print a markdown table of a rocprofv3 --kernel-trace --stats summary of this "
                          "benchmark (run_kernel_stats.csv) and exit")
+    ap.add_argument("--traversal-probe", action="store_true",
+                    help="run the traversal probe (plain copies with each pass's tile traversal at n = 2^24, "
+                         "built by __graft_entry__.build) and print its JSON lines")
     ap.add_argument("--sweep", action="store_true",
                     help="print per-pass kernel times of the plan configurations (tile widths, "
                          "kernel variants, lifts) with streaming references, one JSON object per "
@@ -870,6 +873,15 @@ def main() -> int:
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace))
         return 0
+
+    if args.traversal_probe:
+        # a child process of its own; this process does not touch the GPU
+        import subprocess
+        probe = os.path.join(ROOT, "paper_0811_2535_amd", "traversal_probe")
+        if not os.path.exists(probe):
+            print("bench.py: %s is not built (run __graft_entry__.build())" % probe, file=sys.stderr)
+            return 1
+        return subprocess.run([probe]).returncode
 
     if args.summarize_counters:
         rec = summarize_counters(args.summarize_counters[0], args.summarize_counters[1], args.log2n,

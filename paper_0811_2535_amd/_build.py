@@ -83,5 +83,30 @@ def build(verbose: bool = True, out: str | None = None) -> str:
     return out
 
 
+PROBE_SRC = os.path.join(CSRC, "traversal_probe.hip")
+PROBE_PATH = os.path.join(HERE, "traversal_probe")
+
+
+def build_probe(verbose: bool = True) -> str:
+    """Compile the traversal probe (a measurement program beside the library:
+    plain copies with each pass's tile traversal) to ``traversal_probe``."""
+    t0 = time.time()
+    tmp = PROBE_PATH + ".tmp%d" % os.getpid()
+    cmd = [hipcc()] + compile_flags() + ["-o", tmp, PROBE_SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        if os.path.exists(tmp):
+            os.remove(tmp)
+        raise RuntimeError("hipcc failed compiling traversal_probe.hip")
+    os.replace(tmp, PROBE_PATH)
+    if verbose:
+        print("built %s in %.1fs" % (PROBE_PATH, time.time() - t0), flush=True)
+    return PROBE_PATH
+
+
 if __name__ == "__main__":
     build()
+    build_probe()

@@ -1,0 +1,151 @@
+// Traversal probe: plain copies that move the elements of a complex64
+// transform of n = 2^24 exactly as the library's passes do -- same tiles, same
+// thread layout, same XCD-contiguous tile order -- with no arithmetic and no
+// LDS work, to measure what each pass's access pattern costs by itself.  One
+// JSON object per line on stdout: {"probe": ..., "us": ..., ...}.
+//
+//   pass 1  (two-level 4096 x 4096): 2-column tiles, 512 threads, thread
+//           (c = tid % 2, j = tid / 2) reads rows j + 256 r (r < 16) of
+//           column c, writes the scratch slab S[j1/2][k2][j1%2]; run with
+//           extra dynamic LDS so that 4, 3, 2 or 1 workgroups share a CU
+//   pass 2  4-row tiles, 1024 threads, (c = tid % 4, j = tid / 4) reads
+//           S[k1/2][k2][k1%2] for k1 = j + 256 r, writes X[k2 + 4096 k1]
+//   A, B, C (three-level 256 x 256 x 256): 16-line tiles of 256 points,
+//           256 threads, (c = tid % 16, j = tid / 16), elements j + 16 r;
+//           element (line (lm, ld), i) at (lm << s0) + (ld << s1) + (i << s2)
+//   copy    a contiguous 16-byte-per-lane copy of the same bytes
+#include <hip/hip_runtime.h>
+
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <vector>
+
+#define CHECK(x)                                                                           \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess) {                                                            \
+            fprintf(stderr, "HIP error %s at line %d\n", hipGetErrorString(e_), __LINE__); \
+            exit(1);                                                                       \
+        }                                                                                  \
+    } while (0)
+
+namespace {
+constexpr int L2N = 24, P = 4096, Q = 4096;
+constexpr int64_t N = int64_t(1) << L2N;
+
+// XCD-contiguous order: workgroup g runs tile (g % 8) * (G / 8) + g / 8.
+__device__ __forceinline__ int tile_of(int g, int G) { return (g & 7) * (G >> 3) + (g >> 3); }
+
+__global__ __launch_bounds__(512) void pass1_copy(const float2 *__restrict__ x, float2 *__restrict__ s) {
+    extern __shared__ float reserve[]; // only sized to set the occupancy
+    const int t = tile_of(blockIdx.x, gridDim.x), c = threadIdx.x & 1, j = threadIdx.x >> 1;
+    const int j1 = 2 * t + c;
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = x[int64_t(j1) + int64_t(P) * (j + 256 * r)];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s[int64_t(j1 >> 1) * 2 * Q + 2 * (j + 256 * r) + (j1 & 1)] = v[r];
+    (void)reserve;
+}
+
+__global__ __launch_bounds__(1024) void pass2_copy(const float2 *__restrict__ s, float2 *__restrict__ x) {
+    const int t = tile_of(blockIdx.x, gridDim.x), c = threadIdx.x & 3, j = threadIdx.x >> 2;
+    const int k2 = 4 * t + c;
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int k1 = j + 256 * r;
+        v[r] = s[int64_t(k1 >> 1) * 2 * Q + 2 * k2 + (k1 & 1)];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[int64_t(k2) + int64_t(Q) * (j + 256 * r)] = v[r];
+}
+
+__global__ __launch_bounds__(256) void axis_copy(const float2 *__restrict__ in, float2 *__restrict__ out, int i0, int i1,
+                                                 int i2, int o0, int o1, int o2) {
+    const int t = tile_of(blockIdx.x, gridDim.x), c = threadIdx.x & 15, j = threadIdx.x >> 4;
+    const int line = 16 * t + c, lm = line & 255, ld = line >> 8;
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = j + 16 * r;
+        v[r] = in[(int64_t(lm) << i0) + (int64_t(ld) << i1) + (int64_t(i) << i2)];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = j + 16 * r;
+        out[(int64_t(lm) << o0) + (int64_t(ld) << o1) + (int64_t(i) << o2)] = v[r];
+    }
+}
+
+__global__ __launch_bounds__(256) void stream_copy(const float4 *__restrict__ in, float4 *__restrict__ out, int64_t n4) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n4; i += int64_t(gridDim.x) * blockDim.x)
+        out[i] = in[i];
+}
+} // namespace
+
+int main() {
+    constexpr int SETS = 4, REPS = 20;
+    std::vector<float2 *> a(SETS), b(SETS);
+    for (int k = 0; k < SETS; ++k) {
+        CHECK(hipMalloc(&a[k], N * sizeof(float2)));
+        CHECK(hipMalloc(&b[k], N * sizeof(float2)));
+        CHECK(hipMemset(a[k], 0, N * sizeof(float2)));
+        CHECK(hipMemset(b[k], 0, N * sizeof(float2)));
+    }
+    CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(pass1_copy),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024));
+    hipEvent_t e0, e1;
+    CHECK(hipEventCreate(&e0));
+    CHECK(hipEventCreate(&e1));
+    auto time_us = [&](auto launch) {
+        for (int i = 0; i < SETS; ++i) launch(i);
+        CHECK(hipDeviceSynchronize());
+        CHECK(hipEventRecord(e0, 0));
+        for (int i = 0; i < REPS; ++i) launch(i);
+        CHECK(hipEventRecord(e1, 0));
+        CHECK(hipEventSynchronize(e1));
+        CHECK(hipGetLastError());
+        float ms = 0;
+        CHECK(hipEventElapsedTime(&ms, e0, e1));
+        return 1000.0 * ms / REPS;
+    };
+    printf("{\"probe\": \"copy\", \"what\": \"contiguous copy of 16 n bytes, 16 bytes per lane\", \"us\": %.1f}\n",
+           time_us([&](int i) {
+               hipLaunchKernelGGL(stream_copy, dim3(8192), dim3(256), 0, 0,
+                                  reinterpret_cast<const float4 *>(a[i % SETS]),
+                                  reinterpret_cast<float4 *>(b[i % SETS]), N / 2);
+           }));
+    fflush(stdout);
+    for (int kb : {0, 50, 76, 100}) {
+        int per_cu = 0;
+        CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(pass1_copy), 512,
+                                                          size_t(kb) * 1024));
+        printf("{\"probe\": \"pass 1\", \"workgroups_per_cu\": %d, \"us\": %.1f}\n", per_cu, time_us([&](int i) {
+                   hipLaunchKernelGGL(pass1_copy, dim3(P / 2), dim3(512), size_t(kb) * 1024, 0, a[i % SETS],
+                                      b[i % SETS]);
+               }));
+        fflush(stdout);
+    }
+    printf("{\"probe\": \"pass 2\", \"us\": %.1f}\n", time_us([&](int i) {
+               hipLaunchKernelGGL(pass2_copy, dim3(Q / 4), dim3(1024), 0, 0, a[i % SETS], b[i % SETS]);
+           }));
+    fflush(stdout);
+    struct Axis {
+        const char *name;
+        int in[3], out[3];
+    } axes[] = {{"A", {0, 8, 16}, {0, 8, 16}}, {"B", {0, 16, 8}, {0, 16, 8}}, {"C", {16, 8, 0}, {0, 8, 16}}};
+    for (const Axis &x : axes) {
+        printf("{\"probe\": \"axis pass %s\", \"us\": %.1f}\n", x.name, time_us([&](int i) {
+                   hipLaunchKernelGGL(axis_copy, dim3(int(N / 4096)), dim3(256), 0, 0, a[i % SETS], b[i % SETS],
+                                      x.in[0], x.in[1], x.in[2], x.out[0], x.out[1], x.out[2]);
+               }));
+        fflush(stdout);
+    }
+    for (int k = 0; k < SETS; ++k) {
+        CHECK(hipFree(a[k]));
+        CHECK(hipFree(b[k]));
+    }
+    return 0;
+}
