@@ -145,6 +145,8 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out);
  *                     reaches the output as a NaN.  The transform's
  *                     result is unchanged, bit for bit; the fills cost
  *                     time, and the per-pass timing includes them.
+ *                     FFT_OPT_TILE_ORDER: the tile order of each pass is
+ *                     the one tile_order gives instead of the library's.
  *                     FFT_OPT_THREE_LEVEL takes no two-level options
  *                     (log2_p, lines_per_block2, values_per_thread2,
  *                     scratch_width: FFT_E_ARG); lines_per_block then sets
@@ -158,6 +160,33 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out);
  *                     line, else FFT_E_UNSUPPORTED).  Wider slabs give pass 2
  *                     longer contiguous reads; narrower ones pass 1 longer
  *                     contiguous writes.
+ *   tile_order        with FFT_OPT_TILE_ORDER, the order in which each
+ *                     pass's workgroups take their tiles (else 0, or
+ *                     FFT_E_ARG).  Byte k (k = 0, 1, 2: pass 1 / A, pass 2
+ *                     / B, pass C) is 0x80 for the hardware workgroup order,
+ *                     else (log2 g << 4) | log2 s (at most 0x7f).  s = 1: each
+ *                     XCD takes a contiguous range of tiles, in order (the
+ *                     XCD-contiguous order, on every pass whose grid is a
+ *                     multiple of 8 of at least 16, else the hardware
+ *                     order; the hardware order with FFT_OPT_NO_XCD_REMAP).  s > 1: the range is cut into
+ *                     groups of g adjacent tiles, laid out as s rows of
+ *                     groups, and the XCD's workgroups take the groups
+ *                     column by column, so that the tiles in flight at once
+ *                     lie in s runs spread over the range.  The order
+ *                     changes only where each tile's memory traffic falls
+ *                     in time, never a result bit.  s > 1 with
+ *                     FFT_OPT_NO_XCD_REMAP, bytes beyond the plan's passes,
+ *                     other bytes above 0x7f: FFT_E_ARG; a range that is not a
+ *                     multiple of g s tiles, a grid that is not a multiple
+ *                     of 8 of at least 16, or a persistent pass:
+ *                     FFT_E_UNSUPPORTED.  Without the flag the library
+ *                     uses the orders it measured fastest on MI355X for
+ *                     the shapes it knows (complex64 n = 2^24, one
+ *                     transform: two-level 4096 x 4096 pass 1 g = 2, s =
+ *                     4 and pass 2 g = 1, s = 16; three-level pass A g =
+ *                     1, s = 32 and pass B g = 1, s = 8) and s = 1
+ *                     elsewhere; fft_plan_get_info reports the orders in
+ *                     effect.
  * Kernel variants other than the defaults exist for complex64 two-pass
  * plans with radix 16 and pass lines of 2^10..2^12; asking for one elsewhere
  * returns FFT_E_UNSUPPORTED.  Contradictory flags return FFT_E_ARG.
@@ -188,7 +217,8 @@ enum {
     FFT_OPT_THREE_LEVEL = 256,
     FFT_OPT_SHUFFLE_EXCHANGE = 512,
     FFT_OPT_LDS_PREFETCH = 2048,
-    FFT_OPT_DEBUG_CANARY = 4096
+    FFT_OPT_DEBUG_CANARY = 4096,
+    FFT_OPT_TILE_ORDER = 8192
 };
 typedef struct fft_plan_opts {
     int32_t log2_p;
@@ -199,6 +229,7 @@ typedef struct fft_plan_opts {
     int32_t values_per_thread;
     int32_t values_per_thread2;
     int32_t scratch_width;
+    int32_t tile_order;
 } fft_plan_opts;
 
 /*
@@ -352,7 +383,12 @@ typedef struct fft_plan_info {
     int64_t scratch_bytes, table_bytes;
     int32_t variant_pass1, variant_pass2;
     int32_t length_classes, graph_launch;
-    int32_t precision, reserved0;
+    int32_t precision;
+    /* tile_order: the order each pass's workgroups take their tiles in,
+     * encoded as fft_plan_opts.tile_order (byte k for pass k: 0x80 the
+     * hardware order, 0x00 the XCD-contiguous order without spread);
+     * 0 for uneven batches and the paper's partitioned plan. */
+    int32_t tile_order;
     /* levels: passes of a single-length plan (1, 2 or 3; 0 for uneven
      * batches).  Three-level plans: log2 of n1, n2, n3 (log2_p = log2_q = 0)
      * and pass C's launch in the *_pass3 fields (A and B in pass1, pass2).
@@ -418,7 +454,12 @@ int fft_plan_read_timing(fft_plan *plan, double ms_out[3], int64_t launches_out[
  * cache still holds) and checked
  * against the default plan's output (a configuration whose output differs
  * by more than 1e-4 (complex64) or 1e-10 (complex128) of the largest output
- * is never chosen).  Returns the fastest as *plan_out; if result is not
+ * is never chosen).  A second stage then takes the fastest configuration's
+ * passes in turn and times it with that pass's tiles in the spread orders
+ * s = 2, 4, 8, 16 and 32 (g = 1, FFT_OPT_TILE_ORDER; those the pass's grid
+ * allows), keeping each pass's fastest order before going on to the next
+ * (at most 5 configurations per pass, beyond max_candidates).  Returns the
+ * fastest as *plan_out; if result is not
  * NULL it receives that plan's options (fft_plan_create_ex recreates it) and
  * times.  Tuning is an experiment over implementation variants for one
  * problem size on one machine (Section 8 of the paper); the outcome is
@@ -427,7 +468,7 @@ int fft_plan_read_timing(fft_plan *plan, double ms_out[3], int64_t launches_out[
  * without timing.  If the environment variable LIFTFFT_TUNE_CACHE names a
  * file, outcomes are also kept there across processes: one JSON object per
  * line with the device's architecture name (hipDeviceProp_t::gcnArchName),
- * n, batch, dtype, the eight fields of fft_plan_opts, ms, ms_default,
+ * n, batch, dtype, the nine fields of fft_plan_opts, ms, ms_default,
  * candidates and rejected; a call whose shape is not remembered in the
  * process looks the file up (the last matching line wins; a configuration
  * this build cannot create is tuned again) and returns the stored result
@@ -448,7 +489,7 @@ int fft_plan_create_tuned(int64_t n, int64_t batch, int dtype, int32_t max_candi
                           fft_tune_result *result);
 
 /* ABI version of this header (major*100 + minor). */
-#define LIFTFFT_ABI_VERSION 200
+#define LIFTFFT_ABI_VERSION 201
 int fft_abi_version(void);
 
 #ifdef __cplusplus

@@ -57,13 +57,15 @@ FFT_OPT_SHUFFLE_EXCHANGE = 512
 FFT_OPT_AUTOTUNE = 1024
 FFT_OPT_LDS_PREFETCH = 2048
 FFT_OPT_DEBUG_CANARY = 4096
+FFT_OPT_TILE_ORDER = 8192
 
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("log2_p", ctypes.c_int32), ("radix", ctypes.c_int32),
                 ("lines_per_block", ctypes.c_int32), ("lines_per_block2", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("values_per_thread", ctypes.c_int32),
-                ("values_per_thread2", ctypes.c_int32), ("scratch_width", ctypes.c_int32)]
+                ("values_per_thread2", ctypes.c_int32), ("scratch_width", ctypes.c_int32),
+                ("tile_order", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):
@@ -75,7 +77,8 @@ class TuneResult(ctypes.Structure):
         return {"opts": {"log2_p": o.log2_p, "radix": o.radix, "lines_per_block": o.lines_per_block,
                          "lines_per_block2": o.lines_per_block2, "flags": o.flags,
                          "values_per_thread": o.values_per_thread,
-                         "values_per_thread2": o.values_per_thread2, "scratch_width": o.scratch_width},
+                         "values_per_thread2": o.values_per_thread2, "scratch_width": o.scratch_width,
+                         "tile_order": o.tile_order},
                 "ms": self.ms, "ms_default": self.ms_default, "candidates": self.candidates,
                 "rejected": self.rejected}
 
@@ -92,7 +95,7 @@ class PlanInfo(ctypes.Structure):
                 ("scratch_bytes", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
                 ("variant_pass1", ctypes.c_int32), ("variant_pass2", ctypes.c_int32),
                 ("length_classes", ctypes.c_int32), ("graph_launch", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("tile_order", ctypes.c_int32),
                 ("levels", ctypes.c_int32), ("log2_n1", ctypes.c_int32),
                 ("log2_n2", ctypes.c_int32), ("log2_n3", ctypes.c_int32),
                 ("lines_per_block_pass3", ctypes.c_int32), ("grid_pass3", ctypes.c_int32),
@@ -233,13 +236,14 @@ class Plan:
     def __init__(self, n: int, batch: int = 1, dtype=torch.complex64, log2_p: int = 0,
                  radix: int = 0, lines_per_block: int = 0, lines_per_block2: int = 0,
                  flags: int = 0, values_per_thread: int = 0, values_per_thread2: int = 0,
-                 scratch_width: int = 0):
+                 scratch_width: int = 0, tile_order: int = 0):
         self._h = ctypes.c_void_p()
         self.n, self.batch = int(n), int(batch)
         self.dtype_code = dtype_code(dtype)
         self.torch_dtype = torch.complex64 if self.dtype_code == FFT_C64 else torch.complex128
         opts = PlanOpts(int(log2_p), int(radix), int(lines_per_block), int(lines_per_block2),
-                        int(flags), int(values_per_thread), int(values_per_thread2), int(scratch_width))
+                        int(flags), int(values_per_thread), int(values_per_thread2), int(scratch_width),
+                        int(tile_order))
         rc = lib().fft_plan_create_ex(self.n, self.batch, self.dtype_code, ctypes.byref(opts),
                                       ctypes.byref(self._h))
         _check(rc, "fft_plan_create_ex(n=%d, batch=%d)" % (self.n, self.batch))

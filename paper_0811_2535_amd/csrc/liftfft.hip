@@ -83,6 +83,10 @@ struct PassArgs {
     int32_t log2h;
     int32_t conj_in, conj_out;
     int32_t xcd_remap;
+    // XCD-contiguous order with spread (0 = off): the tiles of an XCD's range
+    // form groups of 2^tile_log2g adjacent tiles, and the groups that run at
+    // the same time are 2^tile_log2s apart in the range instead of adjacent.
+    int32_t tile_log2g, tile_log2s;
     int32_t pitch;  // exchange line pitch, in exchange elements
     const int64_t *offsets; // packed uneven batch: first element of each transform (else b*n)
     int64_t total;          // packed uneven batch: elements in the buffer
@@ -107,7 +111,15 @@ template <bool PERSIST> __device__ __forceinline__ int64_t tile_of(const PassArg
     const int64_t g = blockIdx.x, G = gridDim.x;
     if constexpr (!PERSIST) {
         if (k) return -1;
-        return a.xcd_remap ? (g & 7) * (G >> 3) + (g >> 3) : g; // G is a multiple of 8
+        if (!a.xcd_remap) return g;
+        const int64_t per = G >> 3, i = g >> 3; // G is a multiple of 8
+        if (!a.tile_log2s) return (g & 7) * per + i;
+        // per is a multiple of 2^(tile_log2g + tile_log2s): the range holds
+        // 2^tile_log2s rows of `cols` groups, walked column by column
+        const int gl = a.tile_log2g, sl = a.tile_log2s;
+        const int64_t grp = i >> gl, cols = per >> (gl + sl);
+        const int64_t loc = ((grp & ((1 << sl) - 1)) * cols + (grp >> sl)) << gl | (i & ((int64_t(1) << gl) - 1));
+        return (g & 7) * per + loc;
     } else {
         if (a.xcd_remap) { // G and ntiles are multiples of 8
             const int64_t per = a.ntiles >> 3, loc = k * (G >> 3) + (g >> 3);
@@ -1161,6 +1173,7 @@ struct Launch {
     int pitch = 0;
     size_t lds = 0;
     bool remap = false;
+    int spread_log2g = 0, spread_log2s = 0; // tile order within an XCD's range (remapped, not persistent)
 };
 
 } // namespace
@@ -1182,6 +1195,8 @@ struct fft_plan {
     Variant base1, base2, base3; // the variants chosen at creation (precision FP32)
     int log2W = 0;        // scratch slab width (two-pass plans)
     bool no_remap = false;
+    bool tile_order_set = false; // tile orders given by the caller (FFT_OPT_TILE_ORDER)
+    int32_t tile_order = 0;      // their encoding, one byte per pass
     int precision = 0;
     void *dft_ops = nullptr; // matrix-core forms: DFT-matrix operand table (4 KB per form)
     int dft_ops_prec = 0;    // the form whose operands dft_ops holds
@@ -1395,9 +1410,76 @@ bool default_three_level(int t, int dtype, int radix, const Variant &v) {
 // 2^24: 160 us against 166 us with every pass remapped; at 2^22 48.1 against
 // 49.0); from 2^26 on remapping every pass is at least as fast.  Applied
 // after plan creation and after every change of the plan's kernels.
-void apply_remap_policy(fft_plan *p) {
+// Tile order byte b of a launch (0x80 hardware order, else (log2 g << 4) |
+// log2 s): false if the launch cannot take it.  A spread needs the
+// XCD-contiguous order, one tile per workgroup and XCD ranges of whole g x s
+// blocks.
+bool set_tile_order(Launch &L, int b) {
+    L.spread_log2g = L.spread_log2s = 0;
+    const bool one_tile = !L.var.persist && !L.var.lds_prefetch;
+    if (b == 0x80) {
+        L.remap = false;
+        return true;
+    }
+    if (one_tile) L.remap = L.grid % 8 == 0 && L.grid >= 16;
+    const int log2g = b >> 4, log2s = b & 15;
+    if (!log2s) return true;
+    if (!one_tile || !L.remap || (L.grid >> 3) % (int64_t(1) << (log2g + log2s))) return false;
+    L.spread_log2g = log2g;
+    L.spread_log2s = log2s;
+    return true;
+}
+
+int tile_order_byte(const Launch &L) {
+    return L.remap ? (L.spread_log2g << 4) | L.spread_log2s : 0x80;
+}
+
+// Tile orders measured fastest on MI355X for the default kernels of one
+// complex64 transform of 2^24 (per-pass HIP events, four rotating buffer
+// sets).  Two-level 4096 x 4096: pass 1 107 -> 92 us, pass 2 83 -> 75 us;
+// three-level 256^3: pass A 60 -> 56 us, pass B (hardware order by default
+// at this length) 54 -> 47 us.  Other spreads and other shapes measured
+// slower or within noise (at 256 transforms of 2^20 every spread lost up to
+// 2.5x), so every other launch keeps the plain order.
+struct KnownOrder {
+    int passes, pass, log2n, log2T, var, order;
+};
+constexpr KnownOrder known_orders[] = {
+    {2, 0, 24, 1, 2, 0x12}, // g = 2, s = 4
+    {2, 1, 24, 2, 2, 0x04}, // g = 1, s = 16
+    {3, 0, 24, 4, 0, 0x05}, // g = 1, s = 32
+    {3, 1, 24, 4, 0, 0x03}, // g = 1, s = 8
+};
+
+// Workgroup order of each launch of a single-length plan: the caller's tile
+// orders, else the policy above the known orders.  Applied after plan
+// creation and after every change of the plan's kernels (which keeps the
+// grids); FFT_E_UNSUPPORTED if a given order does not fit its launch.
+int apply_remap_policy(fft_plan *p) {
+    Launch *L[3] = {&p->k1, &p->k2, &p->k3};
+    for (Launch *x : {&p->k1, &p->k2, &p->k3, &p->k1_plain}) x->spread_log2g = x->spread_log2s = 0;
+    if (p->tile_order_set) {
+        for (int k = 0; k < p->passes; ++k) {
+            const int b = (p->tile_order >> (8 * k)) & 0xff;
+            if (p->no_remap) L[k]->remap = false; // with FFT_OPT_NO_XCD_REMAP only s = 1 is accepted
+            else if (!set_tile_order(*L[k], b)) return FFT_E_UNSUPPORTED;
+        }
+        return FFT_OK;
+    }
     if (p->passes == 3 && p->log2n <= 24) p->k2.remap = p->k3.remap = false;
-    if (p->no_remap) p->k1.remap = p->k2.remap = p->k3.remap = false;
+    if (p->no_remap) {
+        p->k1.remap = p->k2.remap = p->k3.remap = false;
+        return FFT_OK;
+    }
+    for (const KnownOrder &e : known_orders) {
+        Launch &x = *L[e.pass];
+        if (e.passes != p->passes || e.log2n != p->log2n || p->dtype != FFT_C64 || p->batch != 1 ||
+            x.log2T != e.log2T || x.var.code() != e.var)
+            continue;
+        Launch trial = x;
+        if (set_tile_order(trial, e.order)) x = trial;
+    }
+    return FFT_OK;
 }
 
 constexpr int TIMING_RING = 1024, RING_EVENTS = 4;
@@ -1428,7 +1510,10 @@ int drain_all(const fft_plan *p) {
 
 int launch(const fft_plan *p, const Launch &L, const PassArgs &args, hipStream_t st) {
     if (L.grid <= 0) return FFT_OK;
-    hipLaunchKernelGGL(L.fn, dim3(unsigned(L.grid)), dim3(unsigned(L.threads)), L.lds, st, args);
+    PassArgs a = args;
+    a.tile_log2g = L.spread_log2g;
+    a.tile_log2s = a.xcd_remap && !L.var.persist && !L.var.lds_prefetch ? L.spread_log2s : 0;
+    hipLaunchKernelGGL(L.fn, dim3(unsigned(L.grid)), dim3(unsigned(L.threads)), L.lds, st, a);
     (void)p;
     return hipGetLastError() == hipSuccess ? FFT_OK : FFT_E_HIP;
 }
@@ -1654,7 +1739,7 @@ int shape_plan(fft_plan *p, int64_t n, int64_t batch, int dtype, const fft_plan_
     constexpr int32_t known_flags = FFT_OPT_NO_XCD_REMAP | FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE |
                                     FFT_OPT_PERSISTENT | FFT_OPT_ONE_TILE | FFT_OPT_DENSE |
                                     FFT_OPT_TWO_LEVEL | FFT_OPT_THREE_LEVEL | FFT_OPT_SHUFFLE_EXCHANGE |
-                                    FFT_OPT_LDS_PREFETCH | FFT_OPT_DEBUG_CANARY;
+                                    FFT_OPT_LDS_PREFETCH | FFT_OPT_DEBUG_CANARY | FFT_OPT_TILE_ORDER;
     // the staged pass 1 is a two-level variant of its own
     if ((o.flags & FFT_OPT_LDS_PREFETCH) &&
         (!(o.flags & FFT_OPT_TWO_LEVEL) || (o.flags & (FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE |
@@ -1679,6 +1764,16 @@ int shape_plan(fft_plan *p, int64_t n, int64_t batch, int dtype, const fft_plan_
     if (o.values_per_thread2 != 0 && o.values_per_thread2 != 16 && o.values_per_thread2 != 32)
         return FFT_E_ARG;
     if (o.scratch_width < 0 || (o.scratch_width & (o.scratch_width - 1))) return FFT_E_ARG;
+    if (o.flags & FFT_OPT_TILE_ORDER) {
+        if (o.tile_order & int32_t(0xff000000)) return FFT_E_ARG;
+        for (int k = 0; k < 3; ++k) {
+            const int b = (o.tile_order >> (8 * k)) & 0xff;
+            if ((b & 0x80) && b != 0x80) return FFT_E_ARG;
+            if ((o.flags & FFT_OPT_NO_XCD_REMAP) && b != 0 && b != 0x80 && (b & 15)) return FFT_E_ARG;
+        }
+    } else if (o.tile_order) {
+        return FFT_E_ARG;
+    }
     // Pass-kernel variant: the defaults unless the options ask for another.
     Variant var;
     if (o.values_per_thread) var.emax = o.values_per_thread;
@@ -1795,7 +1890,10 @@ int shape_plan(fft_plan *p, int64_t n, int64_t batch, int dtype, const fft_plan_
         }
     }
     p->no_remap = (o.flags & FFT_OPT_NO_XCD_REMAP) != 0;
-    apply_remap_policy(p);
+    p->tile_order_set = (o.flags & FFT_OPT_TILE_ORDER) != 0;
+    p->tile_order = o.tile_order;
+    if (p->tile_order_set && (o.tile_order >> (8 * p->passes))) return FFT_E_ARG; // bytes beyond the passes
+    if (const int orc = apply_remap_policy(p)) return orc;
     p->base1 = p->k1.var;
     p->base2 = p->k2.var;
     p->base3 = p->k3.var;
@@ -2594,6 +2692,10 @@ int fft_plan_get_info(const fft_plan *p, fft_plan_info *info) {
     info->variant_pass2 = p->passes == 2 ? p->k2.var.code() : 0;
     info->precision = p->precision;
     info->levels = p->ragged ? 0 : p->passes;
+    if (!p->ragged && !p->paper) {
+        const Launch *L[3] = {&p->k1, &p->k2, &p->k3};
+        for (int k = 0; k < p->passes && k < 3; ++k) info->tile_order |= tile_order_byte(*L[k]) << (8 * k);
+    }
     if (p->paper) {
         info->log2_p = p->pp.log2m;
         info->log2_q = p->log2n - p->pp.log2m;
@@ -2682,7 +2784,8 @@ int fft_plan_set_precision(fft_plan *p, int mode) {
     p->k1 = n1;
     p->k2 = n2;
     p->k3 = n3;
-    apply_remap_policy(p);
+    // the same grids as the kernels replaced, which took these orders
+    (void)apply_remap_policy(p);
     p->precision = mode;
     return FFT_OK;
 }
@@ -2822,6 +2925,8 @@ bool tune_file_lookup(const std::string &arch, int64_t n, int64_t batch, int dty
         r.opts.values_per_thread = int32_t(v[5]);
         r.opts.values_per_thread2 = int32_t(v[6]);
         r.opts.scratch_width = int32_t(v[7]);
+        int64_t order = 0; // absent from lines written before tile orders were tuned
+        if (json_int(line, "tile_order", order)) r.opts.tile_order = int32_t(order);
         r.candidates = int32_t(v[8]);
         r.rejected = int32_t(v[9]);
         r.ms = ms;
@@ -2841,11 +2946,12 @@ void tune_file_append(const std::string &arch, int64_t n, int64_t batch, int dty
                              "{\"arch\": \"%s\", \"n\": %lld, \"batch\": %lld, \"dtype\": %d, \"log2_p\": %d, "
                              "\"radix\": %d, \"lines_per_block\": %d, \"lines_per_block2\": %d, \"flags\": %d, "
                              "\"values_per_thread\": %d, \"values_per_thread2\": %d, \"scratch_width\": %d, "
-                             "\"ms\": %.6g, \"ms_default\": %.6g, \"candidates\": %d, \"rejected\": %d}\n",
+                             "\"tile_order\": %d, \"ms\": %.6g, \"ms_default\": %.6g, \"candidates\": %d, "
+                             "\"rejected\": %d}\n",
                              arch.c_str(), (long long)n, (long long)batch, dtype, r.opts.log2_p, r.opts.radix,
                              r.opts.lines_per_block, r.opts.lines_per_block2, r.opts.flags, r.opts.values_per_thread,
-                             r.opts.values_per_thread2, r.opts.scratch_width, r.ms, r.ms_default, r.candidates,
-                             r.rejected);
+                             r.opts.values_per_thread2, r.opts.scratch_width, r.opts.tile_order, r.ms, r.ms_default,
+                             r.candidates, r.rejected);
     if (len <= 0 || len >= int(sizeof line)) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
@@ -3078,6 +3184,39 @@ int fft_plan_create_tuned(int64_t n, int64_t batch, int dtype, int32_t max_candi
             res.opts = cands[i];
         } else {
             fft_plan_destroy(p);
+        }
+    }
+    // Second stage: the tile order of each pass of the chosen configuration
+    // in turn, the other passes keeping the orders in effect.
+    fft_plan_info bi;
+    if (fft_plan_get_info(best, &bi) == FFT_OK && bi.levels >= 1) {
+        int32_t cur = bi.tile_order;
+        for (int k = 0; k < bi.levels; ++k) {
+            for (int log2s = 1; log2s <= 5; ++log2s) {
+                const int32_t order = (cur & ~(0xff << (8 * k))) | (log2s << (8 * k));
+                if (order == cur) continue;
+                fft_plan_opts o = res.opts;
+                o.flags |= FFT_OPT_TILE_ORDER;
+                o.tile_order = order;
+                fft_plan *p = nullptr;
+                if (fft_plan_create_ex(n, batch, dtype, &o, &p) != FFT_OK) continue;
+                const double ms = tune_time(p, b);
+                ++res.candidates;
+                if (ms < 0 || !(tune_diff(b) <= tol)) {
+                    ++res.rejected;
+                    fft_plan_destroy(p);
+                    continue;
+                }
+                if (ms < best_ms) {
+                    fft_plan_destroy(best);
+                    best = p;
+                    best_ms = ms;
+                    res.opts = o;
+                    cur = order;
+                } else {
+                    fft_plan_destroy(p);
+                }
+            }
         }
     }
     (void)hipStreamSynchronize(b.st);

@@ -203,3 +203,36 @@ def test_create_paper_validation():
     assert L.fft_plan_create_paper(1 << 12, 1, 5, 1, 2, ctypes.byref(h)) == -2
     assert L.fft_plan_create_paper(1 << 21, 1, 0, 4, 6, ctypes.byref(h)) == -8
     assert L.fft_plan_create_paper(1 << 12, 1, 0, 1, 2, None) == -4
+
+
+def test_opts_struct_matches_header():
+    """The binding's fft_plan_opts mirrors the header's field list."""
+    from paper_0811_2535_amd.binding import PlanOpts
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct fft_plan_opts {"):text.index("} fft_plan_opts;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = []
+    for decl in re.findall(r"int32_t\s+([^;]+);", body):
+        names += [v.strip() for v in decl.split(",")]
+    assert [f for f, _ in PlanOpts._fields_] == names
+
+
+def test_tile_order_validation():
+    """tile_order without FFT_OPT_TILE_ORDER, bytes above 0x7f other than
+    0x80, a fourth byte, and a spread with FFT_OPT_NO_XCD_REMAP are refused
+    with FFT_E_ARG before any device work."""
+    from paper_0811_2535_amd.binding import FFT_OPT_NO_XCD_REMAP, FFT_OPT_TILE_ORDER, PlanOpts
+    L = _lib()
+    h = ctypes.c_void_p(123)
+
+    def create(flags, order, n=1 << 16):
+        o = PlanOpts(0, 0, 0, 0, flags)
+        o.tile_order = order
+        return L.fft_plan_create_ex(n, 1, 0, ctypes.byref(o), ctypes.byref(h))
+
+    assert create(0, 0x12) == -9
+    for bad in (0x81, 0xff, 0x8100, 0x810000, 0x01000000):
+        assert create(FFT_OPT_TILE_ORDER, bad) == -9, hex(bad)
+    assert create(FFT_OPT_TILE_ORDER | FFT_OPT_NO_XCD_REMAP, 0x02) == -9
+    assert create(FFT_OPT_TILE_ORDER | FFT_OPT_NO_XCD_REMAP, 0x0300) == -9
+    assert h.value is None

@@ -25,7 +25,8 @@ def test_tuned_plan(torch, t, batch, dtype, tol, cands):
     tdt = torch.complex64 if dtype == np.complex64 else torch.complex128
     announce("tune n=2^%d batch=%d %s candidates=%d" % (t, batch, np.dtype(dtype).name, cands))
     plan, res = lf.Plan.tuned(n, batch, tdt, max_candidates=cands)
-    assert 2 <= res["candidates"] <= cands, res
+    # max_candidates bounds the first stage; the tile-order stage adds at most 5 per pass
+    assert 2 <= res["candidates"] <= cands + 5 * plan.info()["levels"], res
     assert 0 < res["ms"] <= res["ms_default"], res
     x_np = datagen.signals(n, batch, dtype, "normal", 500 + t)
     x = to_dev(x_np)
