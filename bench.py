@@ -664,6 +664,7 @@ def measure_three_level(torch, lf, xs, S, steps, warmup, stream, n):
         "ms_per_step": round(ms_step, 5),
         "lines_per_block": [info["lines_per_block_pass1"], info["lines_per_block_pass2"],
                             info["lines_per_block_pass3"]],
+        "tile_order": "%#08x" % info["tile_order"],
         "alg_bytes_per_step": 2 * 3 * bytes_per_launch,
         # the transform against the two-pass method's 32 n bytes (the
         # roofline below counts each of the three passes' own 16 n bytes)
@@ -763,7 +764,8 @@ def run_sweep(torch, lf, log2n: int, sets: int = 4, reps: int = 12) -> int:
               "lines_per_block": [info["lines_per_block_pass1"], info["lines_per_block_pass2"]],
               "threads": [info["threads_pass1"], info["threads_pass2"]],
               "lds": [info["lds_bytes_pass1"], info["lds_bytes_pass2"]],
-              "variants": [info["variant_pass1"], info["variant_pass2"]]})
+              "variants": [info["variant_pass1"], info["variant_pass2"]],
+              "tile_order": "%#08x" % info["tile_order"]})
 
     TWO, THREE = B.FFT_OPT_TWO_LEVEL, B.FFT_OPT_THREE_LEVEL
     SPLIT, FULL = B.FFT_OPT_SPLIT_EXCHANGE, B.FFT_OPT_FULL_EXCHANGE
@@ -794,6 +796,27 @@ def run_sweep(torch, lf, log2n: int, sets: int = 4, reps: int = 12) -> int:
         plan_times("two-level split p = 2^%d" % lp, flags=TWO, log2_p=lp)
     plan_times("two-level, hardware workgroup order", flags=TWO | B.FFT_OPT_NO_XCD_REMAP)
     plan_times("three-level, hardware workgroup order", flags=THREE | B.FFT_OPT_NO_XCD_REMAP)
+    # Tile orders (byte k: pass k's (log2 g << 4) | log2 s; 0x80 hardware order)
+    ORD = B.FFT_OPT_TILE_ORDER
+    plan_times("two-level, XCD-contiguous order without spread (0x0000)", flags=TWO | ORD, tile_order=0)
+    for ls in range(1, 6):
+        plan_times("two-level, pass 1 order g 1, s %d (0x04%02x)" % (1 << ls, ls), flags=TWO | ORD,
+                   tile_order=0x0400 | ls)
+    for lg in (1, 2, 3):
+        plan_times("two-level, pass 1 order g %d, s 4 (0x04%02x)" % (1 << lg, (lg << 4) | 2), flags=TWO | ORD,
+                   tile_order=0x0400 | (lg << 4) | 2)
+    for ls in range(1, 6):
+        plan_times("two-level, pass 2 order g 1, s %d (0x%02x12)" % (1 << ls, ls), flags=TWO | ORD,
+                   tile_order=(ls << 8) | 0x12)
+    plan_times("three-level, orders without spread, B and C hardware (0x808000)", flags=THREE | ORD,
+               tile_order=0x808000)
+    for ls in range(1, 7):
+        plan_times("three-level, pass A order g 1, s %d (0x8003%02x)" % (1 << ls, ls), flags=THREE | ORD,
+                   tile_order=0x800300 | ls)
+    for ls in range(1, 7):
+        plan_times("three-level, pass B order g 1, s %d (0x80%02x05)" % (1 << ls, ls), flags=THREE | ORD,
+                   tile_order=0x800005 | (ls << 8))
+    plan_times("three-level, pass C XCD-contiguous (0x000305)", flags=THREE | ORD, tile_order=0x000305)
     return 0
 
 
@@ -835,6 +858,79 @@ def run_lift_sweep(torch, lf, sizes, sets: int = 4, reps: int = 10) -> int:
     return 0
 
 
+def run_order_sweep(torch, lf, shapes, rounds: int = 3) -> int:
+    """Tile orders per pass of the library's default plan (complex64), one
+    shape at a time, "LOG2N" or "LOG2NxBATCH": starting from the XCD-contiguous
+    order without spread, each pass in turn is timed in the hardware order
+    and in spread orders (g 1, s 2..32; g 2, s 4 and 8) with the other passes
+    at their best so far, and keeps the fastest.  Times are medians over
+    `rounds` rounds of 20 executes (forward and inverse alternating, four
+    rotating buffer sets, per-pass HIP events).  One JSON object per
+    candidate; the last line of each shape holds the chosen orders and the
+    library's own default orders, both timed again."""
+    from paper_0811_2535_amd import binding as B
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream(dev)
+    for shape in shapes:
+        t, batch = (int(v) for v in shape.split("x")) if "x" in shape else (int(shape), 1)
+        n = 1 << t
+        nsets = 4 if n * batch <= 1 << 26 else 2
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(2)
+        xs = [torch.randn(batch, n, dtype=torch.complex64, device=dev, generator=gen) for _ in range(nsets)]
+        ys = [torch.empty_like(x) for x in xs]
+
+        def timed(**kw):
+            try:
+                p = lf.Plan(n, batch, torch.complex64, **kw)
+            except B.FFTError as ex:
+                return None, ex.name
+            info = p.info()
+            for i in range(2 * nsets):
+                p.execute(xs[i % nsets], ys[i % nsets], -1 if i % 2 == 0 else 1, st)
+            torch.cuda.synchronize()
+            p.set_timing(True)
+            p.read_timing(reset=True)
+            per_round = []
+            for _ in range(rounds):
+                for i in range(20):
+                    p.execute(xs[i % nsets], ys[i % nsets], -1 if i % 2 == 0 else 1, st)
+                ms, cnt = p.read_timing(reset=True)
+                per_round.append([ms[k] / cnt[k] * 1e3 for k in range(3) if cnt[k]])
+            p.set_timing(False)
+            p.destroy()
+            per = [round(sorted(r[k] for r in per_round)[rounds // 2], 1) for k in range(len(per_round[0]))]
+            return per, info
+
+        per0, info0 = timed()
+        if per0 is None:
+            print(json.dumps({"shape": shape, "unsupported": info0}), flush=True)
+            continue
+        levels = info0["levels"]
+        order = 0
+        per_best, _ = timed(flags=B.FFT_OPT_TILE_ORDER, tile_order=order)
+        print(json.dumps({"shape": shape, "order": "%#08x" % order, "us": per_best}), flush=True)
+        for k in range(levels):
+            for b in (0x80, 0x01, 0x02, 0x03, 0x04, 0x05, 0x12, 0x13):
+                cand = (order & ~(0xff << (8 * k))) | (b << (8 * k))
+                per, info = timed(flags=B.FFT_OPT_TILE_ORDER, tile_order=cand)
+                if per is None:
+                    print(json.dumps({"shape": shape, "order": "%#08x" % cand, "unsupported": info}), flush=True)
+                    continue
+                print(json.dumps({"shape": shape, "order": "%#08x" % cand, "us": per}), flush=True)
+                if sum(per) < sum(per_best):
+                    order, per_best = cand, per
+        chosen, _ = timed(flags=B.FFT_OPT_TILE_ORDER, tile_order=order)
+        plain, _ = timed(flags=B.FFT_OPT_TILE_ORDER, tile_order=0)
+        default, info = timed()
+        print(json.dumps({"shape": shape, "levels": levels, "chosen": "%#08x" % order, "chosen_us": chosen,
+                          "plain_us": plain, "default": "%#08x" % info["tile_order"], "default_us": default,
+                          "gain_chosen_vs_plain": round(sum(plain) / sum(chosen), 3)}), flush=True)
+        del xs, ys
+        torch.cuda.empty_cache()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -865,6 +961,9 @@ def main() -> int:
     ap.add_argument("--sweep-lifts", metavar="LOG2N,...",
                     help="print two-level against three-level per-pass times at the given lengths "
                          "(e.g. 20,22,23,24,25,26,28) and exit")
+    ap.add_argument("--sweep-orders", metavar="SHAPE,...",
+                    help="search each pass's tile order for the default plans of the given shapes "
+                         "(LOG2N or LOG2NxBATCH, complex64, e.g. 22,24,20x16) and exit")
     ap.add_argument("--copy-reps", type=int, default=10,
                     help="device-to-device copies of one pass's bytes, timed for context and "
                          "used as the known-size reference kernel for HBM counters")
@@ -918,6 +1017,8 @@ def main() -> int:
         return run_sweep(torch, lf, args.log2n)
     if args.sweep_lifts:
         return run_lift_sweep(torch, lf, [int(v) for v in args.sweep_lifts.split(",")])
+    if args.sweep_orders:
+        return run_order_sweep(torch, lf, args.sweep_orders.split(","))
     n = 1 << args.log2n
     S = max(2, args.sets)
 
@@ -1033,6 +1134,7 @@ def main() -> int:
             "log2_q": info["log2_q"], "radix": info["radix"],
             "lines_per_block": [info["lines_per_block_pass1"], info["lines_per_block_pass2"]],
             "kernel_variants": [info["variant_pass1"], info["variant_pass2"]],
+            "tile_order": "%#06x" % info["tile_order"],
         },
         "hbm": {
             "alg_bytes_per_step": alg_bytes_step,

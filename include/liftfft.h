@@ -179,14 +179,16 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out);
  *                     other bytes above 0x7f: FFT_E_ARG; a range that is not a
  *                     multiple of g s tiles, a grid that is not a multiple
  *                     of 8 of at least 16, or a persistent pass:
- *                     FFT_E_UNSUPPORTED.  Without the flag the library
- *                     uses the orders it measured fastest on MI355X for
- *                     the shapes it knows (complex64 n = 2^24, one
- *                     transform: two-level 4096 x 4096 pass 1 g = 2, s =
- *                     4 and pass 2 g = 1, s = 16; three-level pass A g =
- *                     1, s = 32 and pass B g = 1, s = 8) and s = 1
- *                     elsewhere; fft_plan_get_info reports the orders in
- *                     effect.
+ *                     FFT_E_UNSUPPORTED.  Without the flag, plans created
+ *                     with the default kernels (no kernel-variant, tile
+ *                     width, scratch width or radix option) in FP32 take
+ *                     the orders the library measured fastest on MI355X
+ *                     for the complex64 shapes it knows: one transform of
+ *                     2^24 (two-level 4096 x 4096: 0x0412; three-level:
+ *                     0x800305), of 2^23 (0x0112) and of 2^25 (0x800005),
+ *                     16 transforms of 2^20 (0x8003) and 4096 of 2^12
+ *                     (0x80); every other plan takes s = 1.
+ *                     fft_plan_get_info reports the orders in effect.
  * Kernel variants other than the defaults exist for complex64 two-pass
  * plans with radix 16 and pass lines of 2^10..2^12; asking for one elsewhere
  * returns FFT_E_UNSUPPORTED.  Contradictory flags return FFT_E_ARG.

@@ -1195,7 +1195,8 @@ struct fft_plan {
     Variant base1, base2, base3; // the variants chosen at creation (precision FP32)
     int log2W = 0;        // scratch slab width (two-pass plans)
     bool no_remap = false;
-    bool tile_order_set = false; // tile orders given by the caller (FFT_OPT_TILE_ORDER)
+    bool kernel_defaults = false; // created without kernel-variant, tile-width or radix options
+    bool tile_order_set = false;  // tile orders given by the caller (FFT_OPT_TILE_ORDER)
     int32_t tile_order = 0;      // their encoding, one byte per pass
     int precision = 0;
     void *dft_ops = nullptr; // matrix-core forms: DFT-matrix operand table (4 KB per form)
@@ -1434,21 +1435,29 @@ int tile_order_byte(const Launch &L) {
     return L.remap ? (L.spread_log2g << 4) | L.spread_log2s : 0x80;
 }
 
-// Tile orders measured fastest on MI355X for the default kernels of one
-// complex64 transform of 2^24 (per-pass HIP events, four rotating buffer
-// sets).  Two-level 4096 x 4096: pass 1 107 -> 92 us, pass 2 83 -> 75 us;
-// three-level 256^3: pass A 60 -> 56 us, pass B (hardware order by default
-// at this length) 54 -> 47 us.  Other spreads and other shapes measured
-// slower or within noise (at 256 transforms of 2^20 every spread lost up to
-// 2.5x), so every other launch keeps the plain order.
+// Tile orders measured fastest on MI355X for the library's default plans of
+// these complex64 shapes (the tile-order search of the benchmark: each pass
+// in turn over the hardware order and spreads of g 1, s 2..32 and g 2, s 4
+// and 8, medians of per-pass HIP events over four rotating buffer sets; kept
+// where two searches agreed and the whole transform gained 3% or more).
+// n = 2^24: two-level 4096 x 4096 pass 1 107 -> 92 us, pass 2 83 -> 76 us;
+// three-level 256^3 pass A 61 -> 56 us, pass B 56 -> 46 us.  2^23 (4096 x
+// 2048) pass 2 39 -> 35 us; 2^25 pass A 136 -> 125 us, pass C 111 -> 107
+// us; 16 transforms of 2^20, pass 1 80 -> 61 us; 4096 transforms of 2^12
+// in one pass 68 -> 65 us.  Every other plan keeps the plain order (at 256
+// transforms of 2^20 every spread lost, by up to 2.5x).
 struct KnownOrder {
-    int passes, pass, log2n, log2T, var, order;
+    int passes, log2n, log2p;
+    int64_t batch;
+    int32_t order;
 };
 constexpr KnownOrder known_orders[] = {
-    {2, 0, 24, 1, 2, 0x12}, // g = 2, s = 4
-    {2, 1, 24, 2, 2, 0x04}, // g = 1, s = 16
-    {3, 0, 24, 4, 0, 0x05}, // g = 1, s = 32
-    {3, 1, 24, 4, 0, 0x03}, // g = 1, s = 8
+    {2, 24, 12, 1, 0x0412},   // pass 1 g 2, s 4; pass 2 g 1, s 16
+    {3, 24, 0, 1, 0x800305},  // A g 1, s 32; B g 1, s 8; C hardware order
+    {2, 23, 11, 1, 0x0112},   // pass 1 g 2, s 4; pass 2 g 1, s 2
+    {3, 25, 0, 1, 0x800005},  // A g 1, s 32; B plain; C hardware order
+    {2, 20, 10, 16, 0x8003},  // pass 1 g 1, s 8; pass 2 hardware order
+    {1, 12, 0, 4096, 0x80},   // hardware order
 };
 
 // Workgroup order of each launch of a single-length plan: the caller's tile
@@ -1471,13 +1480,18 @@ int apply_remap_policy(fft_plan *p) {
         p->k1.remap = p->k2.remap = p->k3.remap = false;
         return FFT_OK;
     }
+    if (!p->kernel_defaults || p->dtype != FFT_C64 || p->precision) return FFT_OK;
     for (const KnownOrder &e : known_orders) {
-        Launch &x = *L[e.pass];
-        if (e.passes != p->passes || e.log2n != p->log2n || p->dtype != FFT_C64 || p->batch != 1 ||
-            x.log2T != e.log2T || x.var.code() != e.var)
-            continue;
-        Launch trial = x;
-        if (set_tile_order(trial, e.order)) x = trial;
+        if (e.passes != p->passes || e.log2n != p->log2n || e.log2p != p->log2p || e.batch != p->batch) continue;
+        Launch trial[3] = {p->k1, p->k2, p->k3};
+        bool ok = true;
+        for (int k = 0; k < p->passes && ok; ++k) ok = set_tile_order(trial[k], (e.order >> (8 * k)) & 0xff);
+        if (ok) {
+            p->k1 = trial[0];
+            p->k2 = trial[1];
+            p->k3 = trial[2];
+        }
+        break;
     }
     return FFT_OK;
 }
@@ -1890,6 +1904,9 @@ int shape_plan(fft_plan *p, int64_t n, int64_t batch, int dtype, const fft_plan_
         }
     }
     p->no_remap = (o.flags & FFT_OPT_NO_XCD_REMAP) != 0;
+    p->kernel_defaults = !forced && radix == 16 && !o.lines_per_block && !o.lines_per_block2 &&
+                         !o.scratch_width &&
+                         !(o.flags & (FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE | FFT_OPT_LDS_PREFETCH));
     p->tile_order_set = (o.flags & FFT_OPT_TILE_ORDER) != 0;
     p->tile_order = o.tile_order;
     if (p->tile_order_set && (o.tile_order >> (8 * p->passes))) return FFT_E_ARG; // bytes beyond the passes
@@ -2784,9 +2801,10 @@ int fft_plan_set_precision(fft_plan *p, int mode) {
     p->k1 = n1;
     p->k2 = n2;
     p->k3 = n3;
-    // the same grids as the kernels replaced, which took these orders
-    (void)apply_remap_policy(p);
     p->precision = mode;
+    // the same grids as the kernels replaced, which took these orders (the
+    // measured default orders are the FP32 kernels' only)
+    (void)apply_remap_policy(p);
     return FFT_OK;
 }
 

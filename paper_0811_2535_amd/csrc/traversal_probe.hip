@@ -1,8 +1,9 @@
 // Traversal probe: plain copies that move the elements of a complex64
 // transform of n = 2^24 exactly as the library's passes do -- same tiles, same
-// thread layout, same XCD-contiguous tile order -- with no arithmetic and no
-// LDS work, to measure what each pass's access pattern costs by itself.  One
-// JSON object per line on stdout: {"probe": ..., "us": ..., ...}.
+// thread layout, in the XCD-contiguous tile order and in the spread orders
+// the library uses at this length -- with no arithmetic and no LDS work, to
+// measure what each pass's access pattern costs by itself.  One JSON object
+// per line on stdout: {"probe": ..., "us": ..., ...}.
 //
 //   pass 1  (two-level 4096 x 4096): 2-column tiles, 512 threads, thread
 //           (c = tid % 2, j = tid / 2) reads rows j + 256 r (r < 16) of
@@ -34,12 +35,31 @@ namespace {
 constexpr int L2N = 24, P = 4096, Q = 4096;
 constexpr int64_t N = int64_t(1) << L2N;
 
-// XCD-contiguous order: workgroup g runs tile (g % 8) * (G / 8) + g / 8.
-__device__ __forceinline__ int tile_of(int g, int G) { return (g & 7) * (G >> 3) + (g >> 3); }
+// XCD-contiguous order: workgroup g runs tile (g % 8) * (G / 8) + i, i = g / 8.
+// With a spread (log2s > 0) the XCD's range of G / 8 tiles is cut into groups
+// of 2^log2g tiles laid out as 2^log2s rows, and i walks them column by
+// column (the library's tile orders).
+__host__ __device__ inline int tile_of(int g, int G, int log2g = 0, int log2s = 0) {
+    const int per = G >> 3, i = g >> 3;
+    if (!log2s) return (g & 7) * per + i;
+    const int grp = i >> log2g, cols = per >> (log2g + log2s);
+    return (g & 7) * per + ((((grp & ((1 << log2s) - 1)) * cols + (grp >> log2s)) << log2g) | (i & ((1 << log2g) - 1)));
+}
+// Whether tile_of(., G, log2g, log2s) is a permutation of 0 .. G-1.
+bool order_is_permutation(int G, int log2g, int log2s) {
+    if (G % 8 || ((G >> 3) % (1 << (log2g + log2s)))) return false;
+    std::vector<char> seen(G, 0);
+    for (int g = 0; g < G; ++g) {
+        const int t = tile_of(g, G, log2g, log2s);
+        if (t < 0 || t >= G || seen[t]++) return false;
+    }
+    return true;
+}
 
-__global__ __launch_bounds__(512) void pass1_copy(const float2 *__restrict__ x, float2 *__restrict__ s) {
+__global__ __launch_bounds__(512) void pass1_copy(const float2 *__restrict__ x, float2 *__restrict__ s, int lg,
+                                                  int ls) {
     extern __shared__ float reserve[]; // only sized to set the occupancy
-    const int t = tile_of(blockIdx.x, gridDim.x), c = threadIdx.x & 1, j = threadIdx.x >> 1;
+    const int t = tile_of(blockIdx.x, gridDim.x, lg, ls), c = threadIdx.x & 1, j = threadIdx.x >> 1;
     const int j1 = 2 * t + c;
     float2 v[16];
 #pragma unroll
@@ -49,8 +69,9 @@ __global__ __launch_bounds__(512) void pass1_copy(const float2 *__restrict__ x, 
     (void)reserve;
 }
 
-__global__ __launch_bounds__(1024) void pass2_copy(const float2 *__restrict__ s, float2 *__restrict__ x) {
-    const int t = tile_of(blockIdx.x, gridDim.x), c = threadIdx.x & 3, j = threadIdx.x >> 2;
+__global__ __launch_bounds__(1024) void pass2_copy(const float2 *__restrict__ s, float2 *__restrict__ x, int lg,
+                                                   int ls) {
+    const int t = tile_of(blockIdx.x, gridDim.x, lg, ls), c = threadIdx.x & 3, j = threadIdx.x >> 2;
     const int k2 = 4 * t + c;
     float2 v[16];
 #pragma unroll
@@ -63,8 +84,8 @@ __global__ __launch_bounds__(1024) void pass2_copy(const float2 *__restrict__ s,
 }
 
 __global__ __launch_bounds__(256) void axis_copy(const float2 *__restrict__ in, float2 *__restrict__ out, int i0, int i1,
-                                                 int i2, int o0, int o1, int o2) {
-    const int t = tile_of(blockIdx.x, gridDim.x), c = threadIdx.x & 15, j = threadIdx.x >> 4;
+                                                 int i2, int o0, int o1, int o2, int lg, int ls) {
+    const int t = tile_of(blockIdx.x, gridDim.x, lg, ls), c = threadIdx.x & 15, j = threadIdx.x >> 4;
     const int line = 16 * t + c, lm = line & 255, ld = line >> 8;
     float2 v[16];
 #pragma unroll
@@ -118,18 +139,39 @@ int main() {
                                   reinterpret_cast<float4 *>(b[i % SETS]), N / 2);
            }));
     fflush(stdout);
+    // the spread orders the library uses at this length (g = 2^lg, s = 2^ls)
+    constexpr int P1G = 1, P1S = 2, P2G = 0, P2S = 4, AG = 0, AS = 5, BG = 0, BS = 3;
+    if (!order_is_permutation(P / 2, P1G, P1S) || !order_is_permutation(Q / 4, P2G, P2S) ||
+        !order_is_permutation(int(N / 4096), AG, AS) || !order_is_permutation(int(N / 4096), BG, BS)) {
+        fprintf(stderr, "tile order is not a permutation\n");
+        return 1;
+    }
     for (int kb : {0, 50, 76, 100}) {
         int per_cu = 0;
         CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(pass1_copy), 512,
                                                           size_t(kb) * 1024));
         printf("{\"probe\": \"pass 1\", \"workgroups_per_cu\": %d, \"us\": %.1f}\n", per_cu, time_us([&](int i) {
                    hipLaunchKernelGGL(pass1_copy, dim3(P / 2), dim3(512), size_t(kb) * 1024, 0, a[i % SETS],
-                                      b[i % SETS]);
+                                      b[i % SETS], 0, 0);
+               }));
+        fflush(stdout);
+    }
+    for (int kb : {0, 76}) {
+        int per_cu = 0;
+        CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(pass1_copy), 512,
+                                                          size_t(kb) * 1024));
+        printf("{\"probe\": \"pass 1\", \"order\": \"g 2, s 4\", \"workgroups_per_cu\": %d, \"us\": %.1f}\n",
+               per_cu, time_us([&](int i) {
+                   hipLaunchKernelGGL(pass1_copy, dim3(P / 2), dim3(512), size_t(kb) * 1024, 0, a[i % SETS],
+                                      b[i % SETS], P1G, P1S);
                }));
         fflush(stdout);
     }
     printf("{\"probe\": \"pass 2\", \"us\": %.1f}\n", time_us([&](int i) {
-               hipLaunchKernelGGL(pass2_copy, dim3(Q / 4), dim3(1024), 0, 0, a[i % SETS], b[i % SETS]);
+               hipLaunchKernelGGL(pass2_copy, dim3(Q / 4), dim3(1024), 0, 0, a[i % SETS], b[i % SETS], 0, 0);
+           }));
+    printf("{\"probe\": \"pass 2\", \"order\": \"g 1, s 16\", \"us\": %.1f}\n", time_us([&](int i) {
+               hipLaunchKernelGGL(pass2_copy, dim3(Q / 4), dim3(1024), 0, 0, a[i % SETS], b[i % SETS], P2G, P2S);
            }));
     fflush(stdout);
     struct Axis {
@@ -139,7 +181,17 @@ int main() {
     for (const Axis &x : axes) {
         printf("{\"probe\": \"axis pass %s\", \"us\": %.1f}\n", x.name, time_us([&](int i) {
                    hipLaunchKernelGGL(axis_copy, dim3(int(N / 4096)), dim3(256), 0, 0, a[i % SETS], b[i % SETS],
-                                      x.in[0], x.in[1], x.in[2], x.out[0], x.out[1], x.out[2]);
+                                      x.in[0], x.in[1], x.in[2], x.out[0], x.out[1], x.out[2], 0, 0);
+               }));
+        fflush(stdout);
+    }
+    for (int k = 0; k < 2; ++k) {
+        const Axis &x = axes[k];
+        const int lg = k ? BG : AG, ls = k ? BS : AS;
+        printf("{\"probe\": \"axis pass %s\", \"order\": \"g 1, s %d\", \"us\": %.1f}\n", x.name, 1 << ls,
+               time_us([&](int i) {
+                   hipLaunchKernelGGL(axis_copy, dim3(int(N / 4096)), dim3(256), 0, 0, a[i % SETS], b[i % SETS],
+                                      x.in[0], x.in[1], x.in[2], x.out[0], x.out[1], x.out[2], lg, ls);
                }));
         fflush(stdout);
     }

@@ -25,20 +25,36 @@ def lf(torch):
 
 
 def test_default_orders(lf, torch):
-    """complex64 n = 2^24, one transform: two-level pass 1 (g 2, s 4) and pass
-    2 (g 1, s 16); three-level pass A (g 1, s 32), pass B (g 1, s 8), pass C
-    in the hardware order.  Two transforms of 2^24, FFT_OPT_NO_XCD_REMAP and
-    other lengths keep the plain orders."""
+    """The measured default orders of the shapes the library knows
+    (complex64, default kernels, FP32); other batches, explicit kernel
+    options, FFT_OPT_NO_XCD_REMAP, the matrix-core forms and other lengths
+    keep the plain orders (pass B and C of a three-level lift up to 2^24 in
+    the hardware order)."""
+    B = lf.binding
     cases = [((1 << 24, 1, dict(log2_p=12)), 0x0412),
+             ((1 << 24, 1, dict(flags=B.FFT_OPT_TWO_LEVEL)), 0x0412),
              ((1 << 24, 1, {}), 0x800305),
+             ((1 << 23, 1, {}), 0x0112),
+             ((1 << 25, 1, {}), 0x800005),
+             ((1 << 20, 16, {}), 0x8003),
+             ((1 << 12, 4096, {}), 0x80),
              ((1 << 24, 2, dict(log2_p=12)), 0x0000),
-             ((1 << 24, 1, dict(log2_p=12, flags=lf.binding.FFT_OPT_NO_XCD_REMAP)), 0x8080),
-             ((1 << 22, 1, {}), 0x0000)]
+             ((1 << 24, 1, dict(log2_p=12, flags=B.FFT_OPT_SPLIT_EXCHANGE)), 0x0000),
+             ((1 << 24, 1, dict(log2_p=12, lines_per_block=2)), 0x0000),
+             ((1 << 24, 1, dict(log2_p=12, flags=B.FFT_OPT_NO_XCD_REMAP)), 0x8080),
+             ((1 << 22, 1, {}), 0x0000),
+             ((1 << 21, 1, dict(flags=B.FFT_OPT_THREE_LEVEL)), 0x808000)]
     for (n, batch, kw), want in cases:
         announce("tile order default n=%d batch=%d %s" % (n, batch, kw))
         plan = lf.Plan(n, batch, torch.complex64, **kw)
         assert plan.info()["tile_order"] == want, (n, batch, kw, hex(plan.info()["tile_order"]))
         plan.destroy()
+    plan = lf.Plan(1 << 24, 1, torch.complex64, log2_p=12)
+    plan.set_precision("bf16x2")
+    assert plan.info()["tile_order"] == 0x0000
+    plan.set_precision("fp32")
+    assert plan.info()["tile_order"] == 0x0412
+    plan.destroy()
 
 
 # (n, batch, dtype, options, orders): the first order is the reference
