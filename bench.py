@@ -808,6 +808,11 @@ def run_sweep(torch, lf, log2n: int, sets: int = 4, reps: int = 12) -> int:
     for ls in range(1, 6):
         plan_times("two-level, pass 2 order g 1, s %d (0x%02x12)" % (1 << ls, ls), flags=TWO | ORD,
                    tile_order=(ls << 8) | 0x12)
+    for o in (0x02, 0x03, 0x13):  # the wider pass-1 tiles in spread orders
+        for vpt, fl, fn in ((32, SPLIT, "split"), (16, FULL, "complex")):
+            plan_times("pass 1 T=4, %d values/thread, %s exchange, order 0x04%02x" % (vpt, fn, o),
+                       flags=TWO | fl | ORD, lines_per_block=4, lines_per_block2=4, values_per_thread=vpt,
+                       values_per_thread2=16, tile_order=0x0400 | o)
     plan_times("three-level, orders without spread, B and C hardware (0x808000)", flags=THREE | ORD,
                tile_order=0x808000)
     for ls in range(1, 7):

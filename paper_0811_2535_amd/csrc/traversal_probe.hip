@@ -14,6 +14,7 @@
 //   A, B, C (three-level 256 x 256 x 256): 16-line tiles of 256 points,
 //           256 threads, (c = tid % 16, j = tid / 16), elements j + 16 r;
 //           element (line (lm, ld), i) at (lm << s0) + (ld << s1) + (i << s2)
+//   pass 1 with 4- and 8-column tiles (512 threads), for comparison
 //   copy    a contiguous 16-byte-per-lane copy of the same bytes
 #include <hip/hip_runtime.h>
 
@@ -67,6 +68,22 @@ __global__ __launch_bounds__(512) void pass1_copy(const float2 *__restrict__ x, 
 #pragma unroll
     for (int r = 0; r < 16; ++r) s[int64_t(j1 >> 1) * 2 * Q + 2 * (j + 256 * r) + (j1 & 1)] = v[r];
     (void)reserve;
+}
+
+// Pass 1's traversal with tiles of T columns (T = 4, 8; 512 threads, thread
+// (c = tid % T, j = tid / T) reads rows j + (512 / T) r): what wider tiles
+// would cost to move, for comparison with the 2-column tiles above.
+template <int T>
+__global__ __launch_bounds__(512) void pass1_wide_copy(const float2 *__restrict__ x, float2 *__restrict__ s, int lg,
+                                                       int ls) {
+    constexpr int R = 512 / T, E = Q / R;
+    const int t = tile_of(blockIdx.x, gridDim.x, lg, ls), c = threadIdx.x % T, j = threadIdx.x / T;
+    const int j1 = T * t + c;
+    float2 v[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) v[r] = x[int64_t(j1) + int64_t(P) * (j + R * r)];
+#pragma unroll
+    for (int r = 0; r < E; ++r) s[int64_t(t) * T * Q + int64_t(T) * (j + R * r) + c] = v[r];
 }
 
 __global__ __launch_bounds__(1024) void pass2_copy(const float2 *__restrict__ s, float2 *__restrict__ x, int lg,
@@ -166,6 +183,27 @@ int main() {
                                       b[i % SETS], P1G, P1S);
                }));
         fflush(stdout);
+    }
+    {
+        struct Wide {
+            int T, lg, ls;
+        } wide[] = {{4, 0, 0}, {4, 0, 3}, {8, 0, 0}, {8, 1, 4}};
+        for (const Wide &w : wide) {
+            if (!order_is_permutation(P / w.T, w.lg, w.ls)) {
+                fprintf(stderr, "tile order is not a permutation\n");
+                return 1;
+            }
+            printf("{\"probe\": \"pass 1, %d-column tiles\", \"order\": \"g %d, s %d\", \"us\": %.1f}\n", w.T,
+                   1 << w.lg, 1 << w.ls, time_us([&](int i) {
+                       if (w.T == 4)
+                           hipLaunchKernelGGL(pass1_wide_copy<4>, dim3(P / 4), dim3(512), 0, 0, a[i % SETS],
+                                              b[i % SETS], w.lg, w.ls);
+                       else
+                           hipLaunchKernelGGL(pass1_wide_copy<8>, dim3(P / 8), dim3(512), 0, 0, a[i % SETS],
+                                              b[i % SETS], w.lg, w.ls);
+                   }));
+            fflush(stdout);
+        }
     }
     printf("{\"probe\": \"pass 2\", \"us\": %.1f}\n", time_us([&](int i) {
                hipLaunchKernelGGL(pass2_copy, dim3(Q / 4), dim3(1024), 0, 0, a[i % SETS], b[i % SETS], 0, 0);
