@@ -64,12 +64,18 @@ CASES = [
     (1 << 16, 64, np.complex64, {}, [0x0000, 0x0101, 0x1313, 0x8004]),
     (1 << 12, 256, np.complex64, {}, [0x00, 0x02, 0x80, 0x13]),
     (1 << 20, 2, np.complex128, {}, [0x0000, 0x0202, 0x8011]),
+    # the other shapes with measured default orders
+    (1 << 23, 1, np.complex64, {}, [0x0000, 0x0112]),
+    (1 << 25, 1, np.complex64, {}, [0x000000, 0x800005]),
+    (1 << 20, 16, np.complex64, {}, [0x0000, 0x8003, 0x0312]),
+    (1 << 12, 4096, np.complex64, {}, [0x00, 0x80]),
 ]
 
 
 @pytest.mark.parametrize("n,batch,dtype,kw,orders", CASES,
                          ids=["c64-2^24-two-level", "c64-2^24-three-level", "c64-2^16x64",
-                              "c64-2^12x256-single", "c128-2^20x2"])
+                              "c64-2^12x256-single", "c128-2^20x2", "c64-2^23", "c64-2^25",
+                              "c64-2^20x16", "c64-2^12x4096-single"])
 def test_orders_change_no_bit(lf, torch, n, batch, dtype, kw, orders):
     x_np = datagen.signals(n, batch, dtype, "normal", 700 + n.bit_length())
     x = to_dev(x_np)
