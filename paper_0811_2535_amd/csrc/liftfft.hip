@@ -1461,9 +1461,12 @@ constexpr KnownOrder known_orders[] = {
 };
 
 // Workgroup order of each launch of a single-length plan: the caller's tile
-// orders, else the policy above the known orders.  Applied after plan
-// creation and after every change of the plan's kernels (which keeps the
-// grids); FFT_E_UNSUPPORTED if a given order does not fit its launch.
+// orders if given; else the orders measured for the plan's shape
+// (known_orders, FP32 plans with the default kernels only); else the plain
+// orders (XCD-contiguous, and the hardware order for passes B and C of a
+// three-level lift up to 2^24).  Applied after plan creation and after every
+// change of the plan's kernels (which keeps the grids); FFT_E_UNSUPPORTED if
+// a given order does not fit its launch.
 int apply_remap_policy(fft_plan *p) {
     Launch *L[3] = {&p->k1, &p->k2, &p->k3};
     for (Launch *x : {&p->k1, &p->k2, &p->k3, &p->k1_plain}) x->spread_log2g = x->spread_log2s = 0;
