@@ -159,6 +159,9 @@ def kernel_label(name: str) -> str:
             parts.append({"1": "FP16 pairs on MFMA", "2": "BF16 pairs on MFMA"}[prec])
         return ", ".join(parts)
     for key, label in (("axis_shuffle_kernel", "axis pass, 256-point lines, shuffle exchange"),
+                       ("pass1_rows_kernel<8>", "pass 1, 4096-point lines, c64, rows per thread, radix 8"),
+                       ("pass1_rows_kernel<16>", "pass 1, 4096-point lines, c64, rows per thread, radix 16"),
+                       ("pass1_dma_kernel", "pass 1, 4096-point lines, c64, staged in LDS by direct loads"),
                        ("ragged_kernel", "uneven batch, persistent lifted passes"),
                        ("block_phase", "paper's plan, block phase"), ("cyclic_phase", "paper's plan, cyclic phase"),
                        ("twiddle_table_kernel", "FP64 weight tables"), ("dft_operand_table", "MFMA operand table"),
@@ -808,6 +811,11 @@ def run_sweep(torch, lf, log2n: int, sets: int = 4, reps: int = 12) -> int:
     for ls in range(1, 6):
         plan_times("two-level, pass 2 order g 1, s %d (0x%02x12)" % (1 << ls, ls), flags=TWO | ORD,
                    tile_order=(ls << 8) | 0x12)
+    ROWS = B.FFT_OPT_ROW_LANES
+    for vpt in (16, 32):  # pass 1 with whole rows per thread (8 rows radix 8, 16 rows radix 16)
+        for o in (0x0400, 0x0401, 0x0412, 0x0421):
+            plan_times("pass 1 with rows per thread, %d values/thread, order %#06x" % (vpt, o), flags=TWO | ROWS | ORD,
+                       values_per_thread=vpt, tile_order=o)
     for o in (0x02, 0x03, 0x13):  # the wider pass-1 tiles in spread orders
         for vpt, fl, fn in ((32, SPLIT, "split"), (16, FULL, "complex")):
             plan_times("pass 1 T=4, %d values/thread, %s exchange, order 0x04%02x" % (vpt, fn, o),

@@ -135,6 +135,16 @@ int fft_plan_create(int64_t n, int64_t batch, int dtype, fft_plan **plan_out);
  *                     options FFT_E_ARG.  Inputs not 16-byte aligned run
  *                     the plain pass 1.  A measured alternative: slower
  *                     than the default pass 1 at n = 2^24.
+ *                     FFT_OPT_ROW_LANES (with FFT_OPT_TWO_LEVEL only):
+ *                     pass 1 over 4096-point complex64 columns, 2 per
+ *                     tile, with each thread owning whole rows of the
+ *                     tile (one 16-byte load per row for both columns)
+ *                     instead of one column of a row; same tile, weights
+ *                     and scratch layout.  values_per_thread 16 (default:
+ *                     512 threads, radix-8 stages) or 32 (256 threads,
+ *                     radix 16) sets this pass 1 alone.  Other shapes
+ *                     return FFT_E_UNSUPPORTED, other kernel-variant
+ *                     options FFT_E_ARG.
  *                     FFT_OPT_DEBUG_CANARY (a debug mode, any plan of
  *                     fft_plan_create_ex): every execute first fills the
  *                     scratch array, and `out` wherever a pass reads
@@ -220,7 +230,8 @@ enum {
     FFT_OPT_SHUFFLE_EXCHANGE = 512,
     FFT_OPT_LDS_PREFETCH = 2048,
     FFT_OPT_DEBUG_CANARY = 4096,
-    FFT_OPT_TILE_ORDER = 8192
+    FFT_OPT_TILE_ORDER = 8192,
+    FFT_OPT_ROW_LANES = 16384
 };
 typedef struct fft_plan_opts {
     int32_t log2_p;

@@ -58,6 +58,7 @@ FFT_OPT_AUTOTUNE = 1024
 FFT_OPT_LDS_PREFETCH = 2048
 FFT_OPT_DEBUG_CANARY = 4096
 FFT_OPT_TILE_ORDER = 8192
+FFT_OPT_ROW_LANES = 16384
 
 
 class PlanOpts(ctypes.Structure):

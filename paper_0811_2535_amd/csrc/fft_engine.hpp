@@ -268,6 +268,10 @@ template <int AUX = 0>
 __device__ __forceinline__ double2 buf_load(const double2 *, rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
 }
+// 16 bytes at once: two adjacent complex64 elements.
+__device__ __forceinline__ float4 buf_load_pair(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
 template <int AUX = 0> __device__ __forceinline__ void buf_store(float2 v, rsrc_t r, uint32_t voff, uint32_t soff) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, AUX);
 }
@@ -419,6 +423,79 @@ __device__ __forceinline__ void run_stages(C *v, void *line_base, const C *twl, 
             }
         }
         run_stages<C, N, RMAX, E, SPLIT, STG + 1, LDS_ONLY>(v, line_base, twl, j);
+    }
+}
+
+// The same schedule for NL lines per thread, split exchange only: thread j
+// holds, for each line l, the values run_stages' thread j holds for one
+// line (v[l], same slots), and line l's exchange array starts at
+// lines + l * pitch.  Each exchange writes every line's part, then one
+// barrier pair serves them all.
+template <typename C, int N, int RMAX, int E, int NL, int STG = 0>
+__device__ __forceinline__ void run_stages_lines(C (&v)[NL][E], decltype(C::x) *lines, int pitch, const C *twl,
+                                                 int j) {
+    using Real = decltype(C::x);
+    constexpr int TPL = N / E;
+    constexpr int NST = sched_nstages(N, RMAX);
+    constexpr int R = sched_radix(N, RMAX, STG);
+    constexpr int NS = sched_ns(N, RMAX, STG);
+    constexpr int NB = E / R;
+    if constexpr (STG > 0 && NS > 1) {
+        constexpr int ROW = R + 1, LO = tw_lo_rows(N, RMAX, STG);
+        constexpr int OFF = tw_stage_off(N, RMAX, STG);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int k = (j + i * TPL) & (NS - 1);
+            const C *lo = twl + OFF + (k & 15) * ROW;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                C w = lo[r];
+                if constexpr (NS > 16) w = cmul(w, twl[OFF + (LO + (k >> 4)) * ROW + r]);
+#pragma unroll
+                for (int l = 0; l < NL; ++l) v[l][i * R + r] = cmulc(v[l][i * R + r], w);
+            }
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+#pragma unroll
+        for (int i = 0; i < NB; ++i) dft<R>(&v[l][i * R]);
+    if constexpr (STG + 1 < NST) {
+        constexpr int R2 = sched_radix(N, RMAX, STG + 1), NB2 = E / R2;
+        // Real parts, then imaginary parts (the second write reads only .y,
+        // which the first read left alone).
+#pragma unroll
+        for (int part = 0; part < 2; ++part) {
+            if (STG > 0 || part > 0) __syncthreads(); // earlier readers of the arrays are done
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                Real *line = lines + l * pitch;
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    const int b = j + i * TPL;
+                    const int base = (b / NS) * NS * R + (b & (NS - 1));
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        line[lpad<N>(base + r * NS)] = part ? v[l][i * R + r].y : v[l][i * R + r].x;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                const Real *line = lines + l * pitch;
+#pragma unroll
+                for (int i = 0; i < NB2; ++i) {
+                    const int b = j + i * TPL;
+#pragma unroll
+                    for (int r = 0; r < R2; ++r) {
+                        const Real x = line[lpad<N>(b + r * (N / R2))];
+                        if (part) v[l][i * R2 + r].y = x;
+                        else v[l][i * R2 + r].x = x;
+                    }
+                }
+            }
+        }
+        run_stages_lines<C, N, RMAX, E, NL, STG + 1>(v, lines, pitch, twl, j);
     }
 }
 

@@ -873,6 +873,112 @@ __global__ __launch_bounds__(DMA_THREADS, 1) void pass1_dma_kernel(PassArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Pass 1 over 4096-point complex64 columns, two columns per tile, with each
+// thread owning whole rows of the tile: with E values per column, thread j
+// (N / E threads) loads the two columns' elements of rows j + (N / E) s
+// (s < E), one 16-byte load per row, and runs butterfly j of both columns
+// through a radix-E stage schedule (run_stages_lines: one split-exchange
+// array per column, one barrier pair per exchange for both).  A wavefront
+// load instruction then covers 64 rows of the tile, where the generic pass 1
+// (two threads per row, one per column) covers 32; the tile, the weights and
+// the scratch layout are the same (slabs S[j1/2][k2][j1%2]), and each row of
+// a slab is stored as two 8-byte halves.  E = 16: 256 threads, radix 16;
+// E = 8: 512 threads, radix 8 (four stages, the same registers per thread
+// as the generic kernel).
+constexpr int ROWS_N = 4096, ROWS_T = 2;
+template <int E> constexpr int rows_threads() { return ROWS_N / E; }
+
+template <int E>
+__global__ __launch_bounds__(rows_threads<E>()) void pass1_rows_kernel(PassArgs a) {
+    using C = float2;
+    constexpr uint32_t ES = sizeof(C);
+    constexpr int N = ROWS_N, T = ROWS_T, TPL = N / E, NTHR = TPL, RMAX = E;
+    constexpr int TW = tw_total(N, RMAX), TW_PER = (TW + NTHR - 1) / NTHR, EP = T * (E + 1);
+    static_assert(EP <= NTHR, "one weight factor per thread");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int64_t t = tile_of<false>(a, 0);
+    if (t < 0) return; // workgroup-uniform
+    float *xch = reinterpret_cast<float *>(smem_raw);
+    C *twl = reinterpret_cast<C *>(smem_raw + lds_tile_bytes(N, RMAX, T, a.pitch, sizeof(float)));
+    C *ep = reinterpret_cast<C *>(smem_raw + lds_ep_offset(N, RMAX, T, a.pitch, sizeof(float), sizeof(C)));
+    const int tid = threadIdx.x, j = tid;
+    const C *__restrict__ in = static_cast<const C *>(a.in);
+    C *__restrict__ out = static_cast<C *>(a.out);
+    const C *__restrict__ tw = static_cast<const C *>(a.tw);
+    const C *__restrict__ hi = static_cast<const C *>(a.tw_hi);
+    const C *__restrict__ lo = static_cast<const C *>(a.tw_lo);
+    const int64_t pmask = (int64_t(1) << a.log2p) - 1;
+    const int64_t line0 = t * T, b = line0 >> a.log2p, j10 = line0 & pmask;
+    const int64_t tb = a.offsets ? a.offsets[b] : b * a.n; // first element of transform b
+    const uint32_t lomask = (1u << a.log2h) - 1, nmask = uint32_t(a.n - 1);
+
+    // Table entries first (global loads complete in order, so an entry
+    // loaded after the data would wait for it): stage twiddles, this
+    // thread's weights w_n^(j1 j) of both columns, and one per-slot factor
+    // w_n^(j1 TPL s) (thread c (E + 1) + s; the last slot of each column is
+    // padding).  Unused slots read entry 0.
+    C twr[TW_PER];
+#pragma unroll
+    for (int k = 0; k < TW_PER; ++k) {
+        const int i = tid + k * NTHR, g = i < TW ? tw_source<N, RMAX>(i) : -1;
+        twr[k] = tw[g < 0 ? 0 : g];
+    }
+    C ahi[T], alo[T];
+#pragma unroll
+    for (int c = 0; c < T; ++c) {
+        const uint32_t xa = (uint32_t(j10 + c) * uint32_t(j)) & nmask;
+        ahi[c] = hi[xa >> a.log2h];
+        alo[c] = lo[xa & lomask];
+    }
+    const int ec = tid / (E + 1), es = tid - ec * (E + 1);
+    const bool ep_writer = tid < EP && es < E;
+    const uint32_t xp = ep_writer ? (uint32_t(j10 + ec) * uint32_t(es * TPL)) & nmask : 0u;
+    const C phi = hi[xp >> a.log2h], plo = lo[xp & lomask];
+
+    // Data: row k = j + TPL s of the tile holds columns j10 and j10 + 1 at
+    // element (j10 + k p) of the transform.
+    C v[T][E];
+    {
+        const rsrc_t src = make_rsrc(in + tb + j10, uint32_t(a.n - j10) * ES);
+        const uint32_t lane = (uint32_t(j) << a.log2p) * ES;
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const float4 q = buf_load_pair(src, lane, (uint32_t(s * TPL) << a.log2p) * ES);
+            v[0][s] = mk<C>(q.x, q.y);
+            v[1][s] = mk<C>(q.z, q.w);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < TW_PER; ++k) {
+        const int i = tid + k * NTHR;
+        if (i < TW && tw_source<N, RMAX>(i) >= 0) twl[i] = twr[k];
+    }
+    if (ep_writer) ep[tid] = cmul(phi, plo); // published by the stage loop's first barrier
+    C A[T];
+#pragma unroll
+    for (int c = 0; c < T; ++c) A[c] = cmul(ahi[c], alo[c]);
+    const float sin_ = a.conj_in ? -1.f : 1.f;
+#pragma unroll
+    for (int c = 0; c < T; ++c)
+#pragma unroll
+        for (int s = 0; s < E; ++s) v[c][s] = scale_im(v[c][s], sin_);
+
+    run_stages_lines<C, N, RMAX, E, T>(v, xch, a.pitch, twl, j);
+
+    // Output k2 = j + TPL s of column c, times w_n^-(j1 k2), to slab
+    // S[j1/2][k2][c]: the two halves of one 16-byte slab row.
+    const rsrc_t dst = make_rsrc(out + tb + (j10 << a.log2q), uint32_t(T << a.log2q) * ES);
+    const uint32_t lane = (uint32_t(j) << 1) * ES;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const uint32_t off = (uint32_t(s * TPL) << 1) * ES;
+        buf_store(cmulc(v[0][s], cmul(A[0], ep[s])), dst, lane, off);
+        __asm__ volatile("" ::: "memory"); // two 8-byte stores, not one 16-byte store
+        buf_store(cmulc(v[1][s], cmul(A[1], ep[E + 1 + s])), dst, lane, off + ES);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Packed batches of uneven power-of-two lengths.  The plan groups the
 // transforms into classes of equal length.  Lengths up to 2^12 run through
 // the single-pass kernel, one launch per class, with `a.offsets` listing
@@ -1032,12 +1138,13 @@ struct Variant {
     int prec = 0;         // PREC_*: radix-16 stages on the matrix cores when nonzero
     bool shuffle = false; // axis passes: stage exchange by wavefront shuffles
     bool lds_prefetch = false; // pass 1: persistent, next tile staged in LDS by direct loads
+    bool rows = false;         // pass 1: each thread owns whole rows of a 2-column tile
     bool is_default() const {
-        return emax == 16 && !split && !persist && !dense && !prec && !shuffle && !lds_prefetch;
+        return emax == 16 && !split && !persist && !dense && !prec && !shuffle && !lds_prefetch && !rows;
     }
     int code() const {
         return (emax == 32 ? 1 : 0) | (split ? 2 : 0) | (persist ? 4 : 0) | (dense ? 8 : 0) | (prec << 4) |
-               (shuffle ? 64 : 0) | (lds_prefetch ? 128 : 0);
+               (shuffle ? 64 : 0) | (lds_prefetch ? 128 : 0) | (rows ? 256 : 0);
     }
 };
 
@@ -1135,6 +1242,11 @@ KernelFn pick_kernel(int dtype, int kind, int log2N, int rmax, const Variant &v)
             return nullptr;
         return &pass1_dma_kernel;
     }
+    if (v.rows) { // complex64 pass 1 over 4096-point columns, 2 per tile, rows per thread, split exchange
+        if (kind != K_PASS1 || dtype != FFT_C64 || rmax != 16 || log2N != 12 || (v.code() & ~1) != (256 | 2))
+            return nullptr;
+        return v.emax == 32 ? &pass1_rows_kernel<16> : &pass1_rows_kernel<8>;
+    }
     if (v.shuffle) { // complex64 axis passes over 256-point lines
         if (kind != K_AXIS || dtype != FFT_C64 || rmax != 16 || log2N != 8 || v.code() != 64) return nullptr;
         return &axis_shuffle_kernel;
@@ -1189,7 +1301,7 @@ struct fft_plan {
     size_t table_bytes = 0;
     const void *tw1 = nullptr, *tw2 = nullptr, *tw_hi = nullptr, *tw_lo = nullptr;
     Launch k1, k2, k3; // k3: third pass of a three-level lift
-    Launch k1_plain;   // pass 1 for inputs the LDS-staged pass 1 cannot load (not 16-byte aligned)
+    Launch k1_plain;   // pass 1 for inputs the LDS-staged or row-lane pass 1 cannot load (not 16-byte aligned)
     int log2n1 = 0, log2n2 = 0, log2n3 = 0; // three-level lift n = n1 n2 n3 (n1 contiguous)
     const void *tw3 = nullptr;
     Variant base1, base2, base3; // the variants chosen at creation (precision FP32)
@@ -1316,6 +1428,10 @@ bool fill_launch(Launch &L, int dtype, int kind, int log2N, int rmax, int log2T,
     L.log2T = log2T;
     L.lines = lines;
     L.threads = (N / vals_per_thread(N, v.emax)) << log2T;
+    if (v.rows) { // fixed shape: 2 columns, E rows per thread (E = 16 for 32 values, else 8)
+        if ((int64_t(1) << log2T) != ROWS_T) return false;
+        L.threads = v.emax == 32 ? rows_threads<16>() : rows_threads<8>();
+    }
     if (L.threads > thread_cap(esize, v)) return false;
     if (v.prec && L.threads % 64) return false; // waves own 64 butterflies per stage
     L.kind = kind;
@@ -1324,7 +1440,12 @@ bool fill_launch(Launch &L, int dtype, int kind, int log2N, int rmax, int log2T,
     // every thread of the workgroup reaches, so no tile may be partial.
     if ((kind == K_AXIS || kind == K_AXIS_WIDE) && (lines & ((int64_t(1) << log2T) - 1))) return false;
     L.ntiles = (lines + (int64_t(1) << log2T) - 1) >> log2T;
-    const TileShape ts = tile_shape(log2N, rmax, esize, log2T, v, kind);
+    TileShape ts = tile_shape(log2N, rmax, esize, log2T, v, kind);
+    if (v.rows) { // radix-E stages over E values of each of the 2 columns, split exchange
+        const int Ec = v.emax / 2;
+        ts.pitch = exchange_pitch(N, ROWS_T, N / Ec, int(esize / 2), true);
+        ts.lds = lds_bytes(N, Ec, ROWS_T, Ec, ts.pitch, int(esize / 2), int(esize), true);
+    }
     if (ts.lds > LDS_BUDGET) return false;
     L.pitch = ts.pitch;
     L.lds = size_t(ts.lds);
@@ -1756,12 +1877,19 @@ int shape_plan(fft_plan *p, int64_t n, int64_t batch, int dtype, const fft_plan_
     constexpr int32_t known_flags = FFT_OPT_NO_XCD_REMAP | FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE |
                                     FFT_OPT_PERSISTENT | FFT_OPT_ONE_TILE | FFT_OPT_DENSE |
                                     FFT_OPT_TWO_LEVEL | FFT_OPT_THREE_LEVEL | FFT_OPT_SHUFFLE_EXCHANGE |
-                                    FFT_OPT_LDS_PREFETCH | FFT_OPT_DEBUG_CANARY | FFT_OPT_TILE_ORDER;
+                                    FFT_OPT_LDS_PREFETCH | FFT_OPT_DEBUG_CANARY | FFT_OPT_TILE_ORDER |
+                                    FFT_OPT_ROW_LANES;
     // the staged pass 1 is a two-level variant of its own
     if ((o.flags & FFT_OPT_LDS_PREFETCH) &&
         (!(o.flags & FFT_OPT_TWO_LEVEL) || (o.flags & (FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE |
                                                          FFT_OPT_PERSISTENT | FFT_OPT_DENSE)) ||
          o.values_per_thread || o.scratch_width || (o.lines_per_block && o.lines_per_block != 2)))
+        return FFT_E_ARG;
+    // so is the row-lane pass 1
+    if ((o.flags & FFT_OPT_ROW_LANES) &&
+        (!(o.flags & FFT_OPT_TWO_LEVEL) || (o.flags & (FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE |
+                                                         FFT_OPT_PERSISTENT | FFT_OPT_DENSE | FFT_OPT_LDS_PREFETCH)) ||
+         o.scratch_width || (o.lines_per_block && o.lines_per_block != 2)))
         return FFT_E_ARG;
     // the shuffle exchange exists for three-level plans only, as the only variant
     if ((o.flags & FFT_OPT_SHUFFLE_EXCHANGE) &&
@@ -1793,7 +1921,8 @@ int shape_plan(fft_plan *p, int64_t n, int64_t batch, int dtype, const fft_plan_
     }
     // Pass-kernel variant: the defaults unless the options ask for another.
     Variant var;
-    if (o.values_per_thread) var.emax = o.values_per_thread;
+    // (with FFT_OPT_ROW_LANES values_per_thread sets the row-lane pass 1 alone)
+    if (o.values_per_thread && !(o.flags & FFT_OPT_ROW_LANES)) var.emax = o.values_per_thread;
     if (o.flags & FFT_OPT_SPLIT_EXCHANGE) var.split = true;
     if (o.flags & FFT_OPT_PERSISTENT) var.persist = true;
     if (o.flags & FFT_OPT_DENSE) var.dense = true;
@@ -1905,11 +2034,24 @@ int shape_plan(fft_plan *p, int64_t n, int64_t batch, int dtype, const fft_plan_
                 !fill_launch(p->k1, dtype, K_PASS1, 12, 16, 1, P * batch, vd, p->device))
                 return FFT_E_UNSUPPORTED;
         }
+        if (o.flags & FFT_OPT_ROW_LANES) {
+            // Pass 1 with whole rows per thread: 4096-point complex64
+            // columns, 2 per tile, slabs of width 2.
+            Variant vr;
+            vr.split = true;
+            vr.rows = true;
+            vr.emax = o.values_per_thread ? o.values_per_thread : 16;
+            p->k1_plain = p->k1; // for inputs not 16-byte aligned
+            if (dtype != FFT_C64 || radix != 16 || p->log2q != 12 || p->log2W != 1 || p->k1.log2T != 1 ||
+                !fill_launch(p->k1, dtype, K_PASS1, 12, 16, 1, P * batch, vr, p->device))
+                return FFT_E_UNSUPPORTED;
+        }
     }
     p->no_remap = (o.flags & FFT_OPT_NO_XCD_REMAP) != 0;
     p->kernel_defaults = !forced && radix == 16 && !o.lines_per_block && !o.lines_per_block2 &&
                          !o.scratch_width &&
-                         !(o.flags & (FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE | FFT_OPT_LDS_PREFETCH));
+                         !(o.flags & (FFT_OPT_SPLIT_EXCHANGE | FFT_OPT_FULL_EXCHANGE | FFT_OPT_LDS_PREFETCH |
+                                      FFT_OPT_ROW_LANES));
     p->tile_order_set = (o.flags & FFT_OPT_TILE_ORDER) != 0;
     p->tile_order = o.tile_order;
     if (p->tile_order_set && (o.tile_order >> (8 * p->passes))) return FFT_E_ARG; // bytes beyond the passes
@@ -2570,10 +2712,11 @@ int launch_plan(const fft_plan *p, const void *in, void *out, int sign, hipStrea
             if (rc == FFT_OK && ev) rc = hipEventRecord(ev[k + 1], st) == hipSuccess ? FFT_OK : FFT_E_HIP;
         }
     } else {
-        // The LDS-staged pass 1 loads 16-byte row pairs: other inputs take
-        // the plain pass-1 kernel.
-        const Launch &K1 =
-            p->k1.var.lds_prefetch && (reinterpret_cast<uintptr_t>(in) & 15) ? p->k1_plain : p->k1;
+        // The LDS-staged and the row-lane pass 1 load 16-byte row pairs:
+        // other inputs take the plain pass-1 kernel.
+        const Launch &K1 = (p->k1.var.lds_prefetch || p->k1.var.rows) && (reinterpret_cast<uintptr_t>(in) & 15)
+                               ? p->k1_plain
+                               : p->k1;
         if (rc == FFT_OK && p->canary) rc = canary_fill(p->scratch, p->scratch_bytes, st);
         a.in = in;
         a.out = p->scratch;
@@ -2774,6 +2917,7 @@ int fft_plan_set_precision(fft_plan *p, int mode) {
         Variant v = base;
         if (mode != FFT_PREC_FP32) {
             v.split = false; // the matrix-core stages exchange complex elements
+            v.rows = false;  // and run in the generic tile layout
             v.prec = mode;
         }
         return fill_launch(L, p->dtype, L.kind, L.log2N, L.rmax, L.log2T, L.lines, v, p->device);

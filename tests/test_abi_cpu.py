@@ -236,3 +236,22 @@ def test_tile_order_validation():
     assert create(FFT_OPT_TILE_ORDER | FFT_OPT_NO_XCD_REMAP, 0x02) == -9
     assert create(FFT_OPT_TILE_ORDER | FFT_OPT_NO_XCD_REMAP, 0x0300) == -9
     assert h.value is None
+
+
+def test_row_lane_option_validation():
+    """FFT_OPT_ROW_LANES without FFT_OPT_TWO_LEVEL, or with another kernel
+    variant, a slab width or another tile width, is refused with FFT_E_ARG
+    before any device work."""
+    from paper_0811_2535_amd.binding import (FFT_OPT_LDS_PREFETCH, FFT_OPT_PERSISTENT, FFT_OPT_ROW_LANES,
+                                             FFT_OPT_SPLIT_EXCHANGE, FFT_OPT_TWO_LEVEL, PlanOpts)
+    L = _lib()
+    h = ctypes.c_void_p(123)
+    TWO = FFT_OPT_TWO_LEVEL
+    for opts in (PlanOpts(12, 0, 0, 0, FFT_OPT_ROW_LANES),
+                 PlanOpts(12, 0, 0, 0, TWO | FFT_OPT_ROW_LANES | FFT_OPT_SPLIT_EXCHANGE),
+                 PlanOpts(12, 0, 0, 0, TWO | FFT_OPT_ROW_LANES | FFT_OPT_PERSISTENT),
+                 PlanOpts(12, 0, 0, 0, TWO | FFT_OPT_ROW_LANES | FFT_OPT_LDS_PREFETCH),
+                 PlanOpts(12, 0, 4, 0, TWO | FFT_OPT_ROW_LANES),
+                 PlanOpts(12, 0, 0, 0, TWO | FFT_OPT_ROW_LANES, 0, 0, 4)):
+        assert L.fft_plan_create_ex(1 << 24, 1, 0, ctypes.byref(opts), ctypes.byref(h)) == -9
+    assert h.value is None

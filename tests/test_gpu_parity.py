@@ -313,6 +313,9 @@ def test_complex128_repeat_determinism(lf, torch):
 
 
 LDS_PREFETCH = 2048  # FFT_OPT_LDS_PREFETCH
+ROW_LANES = 16384  # FFT_OPT_ROW_LANES
+SPLIT = 2  # FFT_OPT_SPLIT_EXCHANGE
+FULL = 4  # FFT_OPT_FULL_EXCHANGE: the generic kernels
 
 
 @pytest.mark.parametrize("t,batch", [(24, 1), (23, 2)])
@@ -345,3 +348,58 @@ def test_lds_staged_pass1(lf, torch, t, batch):
     plan.destroy()
     check_rows(to_np(xd), x, -1, TOL[np.complex64])
     check_rows(to_np(y), x, -1, TOL[np.complex64])
+
+
+@pytest.mark.parametrize("vpt", [16, 32])
+@pytest.mark.parametrize("t,batch", [(24, 1), (23, 2), (17, 3)])
+def test_row_lane_pass1(lf, torch, t, batch, vpt):
+    """Pass 1 with each thread owning whole rows of a 2-column tile (4096-point
+    columns; 2^17 as 32 x 4096), 8 rows per thread with radix-8 stages or 16
+    with radix 16: against the oracle for both signs, against the generic
+    kernels to rounding level, in place, and for an input that is only 8-byte
+    aligned (which takes the generic pass 1)."""
+    n = 1 << t
+    kw = dict(flags=128 | ROW_LANES, log2_p=t - 12, values_per_thread=vpt)
+    x = datagen.signals(n, batch, np.complex64, "normal", 360 + t)
+    plan = lf.Plan(n, batch, torch.complex64, **kw)
+    info = plan.info()
+    plan.destroy()
+    assert info["variant_pass1"] & 256 and info["lines_per_block_pass1"] == 2, info
+    assert info["threads_pass1"] == 8192 // vpt and not info["variant_pass2"] & 1, info  # pass 2 keeps 16 values
+    for sign in (-1, 1):
+        announce("row-lane pass 1 n=2^%d batch=%d vpt=%d sign=%d" % (t, batch, vpt, sign))
+        got = run_plan(lf, x, sign, **kw)
+        check_rows(got, x, sign, TOL[np.complex64])
+        generic = run_plan(lf, x, sign, flags=128 | FULL, log2_p=t - 12)
+        assert_rounding_level(got, generic, ("row-lane", t, sign))
+    announce("row-lane pass 1 n=2^%d vpt=%d in place and 8-byte aligned input" % (t, vpt))
+    plan = lf.Plan(n, batch, torch.complex64, **kw)
+    xd = to_dev(x)
+    plan.execute(xd, xd, -1)
+    buf = torch.zeros(n * batch + 1, dtype=torch.complex64, device="cuda")
+    shifted = buf[1:].view(batch, n)  # 8 bytes past a 16-byte boundary
+    shifted.copy_(to_dev(x))
+    y = torch.empty_like(shifted)
+    plan.execute(shifted, y, -1)
+    torch.cuda.synchronize()
+    plan.destroy()
+    check_rows(to_np(xd), x, -1, TOL[np.complex64])
+    check_rows(to_np(y), x, -1, TOL[np.complex64])
+
+
+def test_row_lane_pass1_refusals(lf, torch):
+    """Shapes the row-lane pass 1 does not cover return FFT_E_UNSUPPORTED;
+    other kernel-variant options with it, or no FFT_OPT_TWO_LEVEL, FFT_E_ARG."""
+    B = lf.binding
+    for kw, code in ((dict(flags=128 | ROW_LANES, log2_p=11), -8),          # 8192-point columns
+                     (dict(flags=128 | ROW_LANES, log2_p=12, lines_per_block=1), -9),
+                     (dict(flags=128 | ROW_LANES | SPLIT, log2_p=12), -9),
+                     (dict(flags=ROW_LANES, log2_p=12), -9)):
+        announce("row-lane refusal %s" % kw)
+        with pytest.raises(lf.FFTError) as e:
+            lf.Plan(1 << 24, 1, torch.complex64, **kw)
+        assert e.value.code == code, (kw, e.value.code)
+    announce("row-lane refusal complex128")
+    with pytest.raises(lf.FFTError) as e:
+        lf.Plan(1 << 24, 1, torch.complex128, flags=128 | ROW_LANES, log2_p=12)
+    assert e.value.code == -8
