@@ -14,7 +14,8 @@
 //   A, B, C (three-level 256 x 256 x 256): 16-line tiles of 256 points,
 //           256 threads, (c = tid % 16, j = tid / 16), elements j + 16 r;
 //           element (line (lm, ld), i) at (lm << s0) + (ld << s1) + (i << s2)
-//   pass 1 with 4- and 8-column tiles (512 threads), for comparison
+//   pass 1 with 4- and 8-column tiles (512 threads), for comparison, and
+//           with each thread owning whole rows of the 2-column tile
 //   copy    a contiguous 16-byte-per-lane copy of the same bytes
 #include <hip/hip_runtime.h>
 
@@ -84,6 +85,27 @@ __global__ __launch_bounds__(512) void pass1_wide_copy(const float2 *__restrict_
     for (int r = 0; r < E; ++r) v[r] = x[int64_t(j1) + int64_t(P) * (j + R * r)];
 #pragma unroll
     for (int r = 0; r < E; ++r) s[int64_t(t) * T * Q + int64_t(T) * (j + R * r) + c] = v[r];
+}
+
+// Pass 1's traversal with each thread owning whole rows of the 2-column tile
+// (the row-lane pass 1): thread j loads both columns of rows j + (N / E) r,
+// one 16-byte load per row, and stores each slab row as two 8-byte halves.
+template <int E>
+__global__ __launch_bounds__(Q / E) void pass1_rows_copy(const float2 *__restrict__ x, float2 *__restrict__ s, int lg,
+                                                       int ls) {
+    constexpr int R = Q / E;
+    const int t = tile_of(blockIdx.x, gridDim.x, lg, ls), j = threadIdx.x;
+    const float4 *col = reinterpret_cast<const float4 *>(x + 2 * int64_t(t));
+    float4 v[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) v[r] = col[int64_t(P / 2) * (j + R * r)];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        float2 *d = s + (int64_t(t) * Q + (j + R * r)) * 2;
+        d[0] = make_float2(v[r].x, v[r].y);
+        __asm__ volatile("" ::: "memory"); // two 8-byte stores, as the pass does
+        d[1] = make_float2(v[r].z, v[r].w);
+    }
 }
 
 __global__ __launch_bounds__(1024) void pass2_copy(const float2 *__restrict__ s, float2 *__restrict__ x, int lg,
@@ -204,6 +226,25 @@ int main() {
                    }));
             fflush(stdout);
         }
+    }
+    for (int ls : {0, 1}) {
+        if (!order_is_permutation(P / 2, 0, ls)) {
+            fprintf(stderr, "tile order is not a permutation\n");
+            return 1;
+        }
+        printf("{\"probe\": \"pass 1, rows per thread, 8 rows (512 threads)\", \"order\": \"g 1, s %d\", "
+               "\"us\": %.1f}\n",
+               1 << ls, time_us([&](int i) {
+                   hipLaunchKernelGGL(pass1_rows_copy<8>, dim3(P / 2), dim3(Q / 8), 0, 0, a[i % SETS], b[i % SETS], 0,
+                                      ls);
+               }));
+        printf("{\"probe\": \"pass 1, rows per thread, 16 rows (256 threads)\", \"order\": \"g 1, s %d\", "
+               "\"us\": %.1f}\n",
+               1 << ls, time_us([&](int i) {
+                   hipLaunchKernelGGL(pass1_rows_copy<16>, dim3(P / 2), dim3(Q / 16), 0, 0, a[i % SETS], b[i % SETS],
+                                      0, ls);
+               }));
+        fflush(stdout);
     }
     printf("{\"probe\": \"pass 2\", \"us\": %.1f}\n", time_us([&](int i) {
                hipLaunchKernelGGL(pass2_copy, dim3(Q / 4), dim3(1024), 0, 0, a[i % SETS], b[i % SETS], 0, 0);
