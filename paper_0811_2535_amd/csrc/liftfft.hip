@@ -883,8 +883,11 @@ __global__ __launch_bounds__(DMA_THREADS, 1) void pass1_dma_kernel(PassArgs a) {
 // (two threads per row, one per column) covers 32; the tile, the weights and
 // the scratch layout are the same (slabs S[j1/2][k2][j1%2]), and each row of
 // a slab is stored as two 8-byte halves.  E = 16: 256 threads, radix 16;
-// E = 8: 512 threads, radix 8 (four stages, the same registers per thread
-// as the generic kernel).
+// E = 8: 512 threads, radix 8 (four stages, the same data registers per
+// thread as the generic kernel).  Selected by FFT_OPT_ROW_LANES only: at
+// n = 2^24 both forms measured slower than the generic pass 1 (the 16-row
+// form holds 168 VGPRs, three 256-thread workgroups per CU; the 8-row form
+// stores its rows as 8-byte halves, a slower traversal).
 constexpr int ROWS_N = 4096, ROWS_T = 2;
 template <int E> constexpr int rows_threads() { return ROWS_N / E; }
 
