@@ -316,6 +316,7 @@ LDS_PREFETCH = 2048  # FFT_OPT_LDS_PREFETCH
 ROW_LANES = 16384  # FFT_OPT_ROW_LANES
 SPLIT = 2  # FFT_OPT_SPLIT_EXCHANGE
 FULL = 4  # FFT_OPT_FULL_EXCHANGE: the generic kernels
+CANARY = 4096  # FFT_OPT_DEBUG_CANARY: NaN-filled scratch, so no stale data can stand in for a missing write
 
 
 @pytest.mark.parametrize("t,batch", [(24, 1), (23, 2)])
@@ -359,7 +360,7 @@ def test_row_lane_pass1(lf, torch, t, batch, vpt):
     kernels to rounding level, in place, and for an input that is only 8-byte
     aligned (which takes the generic pass 1)."""
     n = 1 << t
-    kw = dict(flags=128 | ROW_LANES, log2_p=t - 12, values_per_thread=vpt)
+    kw = dict(flags=128 | ROW_LANES | CANARY, log2_p=t - 12, values_per_thread=vpt)
     x = datagen.signals(n, batch, np.complex64, "normal", 360 + t)
     plan = lf.Plan(n, batch, torch.complex64, **kw)
     info = plan.info()

@@ -85,7 +85,11 @@ def test_orders_change_no_bit(lf, torch, n, batch, dtype, kw, orders):
         ref = None
         for order in orders:
             announce("tile order n=%d batch=%d order=%#x sign=%d" % (n, batch, order, sign))
-            plan = lf.Plan(n, batch, tdt, flags=flags | lf.binding.FFT_OPT_TILE_ORDER, tile_order=order, **kw)
+            # the canary mode fills the scratch array (and `out`) with NaNs before
+            # each execute, so a tile that an order skipped cannot be covered up
+            # by what an earlier plan left in reused memory
+            plan = lf.Plan(n, batch, tdt, flags=flags | lf.binding.FFT_OPT_TILE_ORDER | lf.binding.FFT_OPT_DEBUG_CANARY,
+                           tile_order=order, **kw)
             assert plan.info()["tile_order"] == order, hex(plan.info()["tile_order"])
             y = torch.full_like(x, float("nan"))
             plan.execute(x, y, sign)
