@@ -85,8 +85,10 @@ def test_tuner_cache_file(torch, tmp_path):
     assert rec["candidates"] == res["candidates"] and abs(rec["ms"] - res["ms"]) <= 1e-6 * max(1.0, res["ms"])
     # a later line for the same key, naming a configuration the tuner would
     # not report by itself: the two-level lift 64 x 256
+    # (every option field is set: the tuner's own line may carry a tile order,
+    # which without FFT_OPT_TILE_ORDER in flags would make the line invalid)
     forged = dict(rec, log2_p=6, radix=0, lines_per_block=0, lines_per_block2=0, flags=128, values_per_thread=0,
-                  values_per_thread2=0, scratch_width=0, ms=123.0, ms_default=456.0, candidates=99)
+                  values_per_thread2=0, scratch_width=0, tile_order=0, ms=123.0, ms_default=456.0, candidates=99)
     with open(path, "a") as f:
         f.write(json.dumps(forged) + "\n")
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
