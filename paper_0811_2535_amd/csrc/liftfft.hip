@@ -1569,7 +1569,7 @@ int tile_order_byte(const Launch &L) {
 // 2048) pass 2 39 -> 35 us; 2^25 pass A 136 -> 125 us, pass C 111 -> 107
 // us; 16 transforms of 2^20, pass 1 80 -> 61 us; 4096 transforms of 2^12
 // in one pass 68 -> 65 us.  Every other plan keeps the plain order (at 256
-// transforms of 2^20 every spread lost, by up to 2.5x).
+// transforms of 2^20, for one, no spread won).
 struct KnownOrder {
     int passes, log2n, log2p;
     int64_t batch;
